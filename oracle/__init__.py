@@ -1,0 +1,276 @@
+"""Plain FP64 CPU oracle for 3-D ray-bundle lensing (Killedar et al. 2011).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product library
+(``paper_1110_4894_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``oracle.c`` (one function per step of the method, each
+citing the section or equation it follows).  This module only compiles it with
+gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (portable -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Cosmo(C.Structure):
+    _fields_ = [("omega_m", C.c_double), ("omega_lambda", C.c_double), ("h", C.c_double)]
+
+
+class _Set(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("m", C.c_void_p), ("softening", C.c_double), ("background", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class _Field(C.Structure):
+    _fields_ = [("n_sets", C.c_int32), ("sets", C.c_void_p), ("n_steps", C.c_int32),
+                ("z_nodes", C.c_void_p), ("step_set", C.c_void_p),
+                ("bundle_offset", C.c_int64), ("n_bundles", C.c_int64)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        d, p, i32, i64 = C.c_double, C.c_void_p, C.c_int32, C.c_int64
+        cp = C.POINTER(Cosmo)
+        sig = {
+            "or_G_over_c2": (d, []), "or_H0": (d, [cp]), "or_rho_crit0": (d, [cp]),
+            "or_E": (d, [cp, d]), "or_comoving_distance": (d, [cp, d]),
+            "or_empty_beam_distance": (d, [cp, d]), "or_t0": (d, [cp]),
+            "or_scale_factor": (None, [cp, d, p, p]),
+            "or_prism": (None, [p, p, p, p, p]),
+            "or_field_at": (None, [cp, p, p, p, p]),
+            "or_derivs": (None, [cp, p, d, p, p]),
+            "or_accel": (None, [cp, d, p, d, p, p]),
+            "or_make_schedule": (i32, [d, d, d, i32, d, p, i32, p]),
+            "or_replica_step_sets": (i32, [p, i32, d, i32, p]),
+            "or_build_bundles": (i32, [cp, p, i32, i64, p, d, p]),
+            "or_trace": (i32, [cp, p, i32, i32, i32, i64, p, p, i32]),
+            "or_magnification": (i32, [d, i64, d, p, p, p]),
+            "or_mu_histogram": (i32, [i64, p, i32, d, d, p, p]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cosmo(omega_m: float = 0.3, omega_lambda: float = 0.7, h: float = 0.7) -> Cosmo:
+    return Cosmo(omega_m, omega_lambda, h)
+
+
+# --------------------------------------------------------------------------- background
+def G_over_c2() -> float:
+    return _load().or_G_over_c2()
+
+
+def H0(c: Cosmo) -> float:
+    return _load().or_H0(C.byref(c))
+
+
+def rho_crit0(c: Cosmo) -> float:
+    return _load().or_rho_crit0(C.byref(c))
+
+
+def E(c: Cosmo, z: float) -> float:
+    return _load().or_E(C.byref(c), z)
+
+
+def comoving_distance(c: Cosmo, z: float) -> float:
+    return _load().or_comoving_distance(C.byref(c), z)
+
+
+def empty_beam_distance(c: Cosmo, z: float) -> float:
+    return _load().or_empty_beam_distance(C.byref(c), z)
+
+
+def t0(c: Cosmo) -> float:
+    return _load().or_t0(C.byref(c))
+
+
+def scale_factor(c: Cosmo, t: float):
+    a, ad = C.c_double(), C.c_double()
+    _load().or_scale_factor(C.byref(c), t, C.addressof(a), C.addressof(ad))
+    return a.value, ad.value
+
+
+# --------------------------------------------------------------------------- field
+def prism(lo, hi, p):
+    lo, hi, p = _f64(lo), _f64(hi), _f64(p)
+    U = np.zeros(1)
+    g = np.zeros(3)
+    _load().or_prism(_ptr(lo), _ptr(hi), _ptr(p), _ptr(U), _ptr(g))
+    return U[0], g
+
+
+@dataclass
+class ParticleSet:
+    """One lens volume: FP64 positions (comoving Mpc) and masses (Msun)."""
+    xyz: np.ndarray                     # [n, 3]
+    m: np.ndarray                       # [n]
+    softening: float = 0.0
+    background: bool = False
+    lo: Sequence[float] = (0.0, 0.0, 0.0)
+    hi: Sequence[float] = (0.0, 0.0, 0.0)
+    _keep: list = field(default_factory=list, repr=False)
+
+    def _c(self) -> _Set:
+        xyz = np.asarray(self.xyz, dtype=np.float64).reshape(-1, 3)
+        cols = [np.ascontiguousarray(xyz[:, i]) for i in range(3)] + [_f64(self.m)]
+        self._keep = cols
+        s = _Set()
+        s.n = xyz.shape[0]
+        s.x, s.y, s.z, s.m = (_ptr(a) if a.size else None for a in cols)
+        s.softening = float(self.softening)
+        s.background = 1 if self.background else 0
+        s.lo = (C.c_double * 3)(*[float(v) for v in self.lo])
+        s.hi = (C.c_double * 3)(*[float(v) for v in self.hi])
+        return s
+
+
+def field_at(c: Cosmo, pset: ParticleSet, p):
+    s = pset._c()
+    p = _f64(p)
+    phi = np.zeros(1)
+    g = np.zeros(3)
+    _load().or_field_at(C.byref(c), C.byref(s), _ptr(p), _ptr(phi), _ptr(g))
+    return phi[0], g
+
+
+def derivs(c: Cosmo, Y, phi: float, g):
+    Y, g = _f64(Y), _f64(g)
+    dY = np.zeros(7)
+    _load().or_derivs(C.byref(c), _ptr(Y), float(phi), _ptr(g), _ptr(dY))
+    return dY
+
+
+def accel(c: Cosmo, t: float, k, phi: float, g):
+    k, g = _f64(k), _f64(g)
+    A = np.zeros(4)
+    _load().or_accel(C.byref(c), float(t), _ptr(k), float(phi), _ptr(g), _ptr(A))
+    return A
+
+
+# --------------------------------------------------------------------------- schedule
+def make_schedule(chi_s: float, z_lo: float, z_hi: float, n_fine: int, q: float, capacity: int = 1 << 20):
+    nodes = np.zeros(capacity)
+    n = C.c_int32()
+    rc = _load().or_make_schedule(chi_s, z_lo, z_hi, n_fine, q, _ptr(nodes), capacity, C.addressof(n))
+    if rc != 0:
+        raise ValueError("or_make_schedule failed (%d)" % rc)
+    return nodes[: n.value + 1].copy()
+
+
+def replica_step_sets(nodes, box: float, n_replicas: int):
+    nodes = _f64(nodes)
+    out = np.zeros(len(nodes) - 1, dtype=np.int32)
+    rc = _load().or_replica_step_sets(_ptr(nodes), len(nodes) - 1, box, n_replicas, _ptr(out))
+    if rc != 0:
+        raise ValueError("or_replica_step_sets failed (%d)" % rc)
+    return out
+
+
+# --------------------------------------------------------------------------- hot path
+@dataclass
+class Field:
+    sets: List[ParticleSet]
+    z_nodes: np.ndarray
+    step_set: np.ndarray
+    bundle_offset: int
+    n_bundles: int
+
+
+class _Fields:
+    """Keeps the ctypes structures (and the arrays they point to) alive."""
+
+    def __init__(self, fields: Sequence[Field]):
+        self.keep = []
+        self.arr = (_Field * max(1, len(fields)))()
+        for i, f in enumerate(fields):
+            sets = (_Set * max(1, len(f.sets)))()
+            for j, s in enumerate(f.sets):
+                sets[j] = s._c()
+                self.keep.append(s._keep)
+            nodes = _f64(f.z_nodes)
+            ss = np.ascontiguousarray(f.step_set, dtype=np.int32)
+            self.keep += [sets, nodes, ss]
+            self.arr[i] = _Field(len(f.sets), C.addressof(sets), len(nodes) - 1, _ptr(nodes), _ptr(ss),
+                                 int(f.bundle_offset), int(f.n_bundles))
+        self.n = len(fields)
+
+
+def build_bundles(c: Cosmo, fields: Sequence[Field], theta: np.ndarray, radius: float) -> np.ndarray:
+    theta = _f64(theta).reshape(2, -1)
+    nb = theta.shape[1]
+    rays = np.zeros((8, 9 * nb))
+    fs = _Fields(fields)
+    _load().or_build_bundles(C.byref(c), C.addressof(fs.arr), fs.n, nb, _ptr(theta), float(radius), _ptr(rays))
+    return rays
+
+
+def trace(c: Cosmo, fields: Sequence[Field], rays: np.ndarray, step_begin: int = 0, step_end: int = 2**31 - 1,
+          n_threads: int = 0, flags: Optional[np.ndarray] = None):
+    """Trace in place; returns (rays, flags)."""
+    assert rays.dtype == np.float64 and rays.flags.c_contiguous and rays.shape[0] == 8
+    n_rays = rays.shape[1]
+    if flags is None:
+        flags = np.zeros(n_rays, dtype=np.uint8)
+    fs = _Fields(fields)
+    _load().or_trace(C.byref(c), C.addressof(fs.arr), fs.n, step_begin, step_end, n_rays, _ptr(rays), _ptr(flags),
+                     n_threads)
+    return rays, flags
+
+
+def magnification(chi_s: float, rays: np.ndarray, radius: float):
+    rays = _f64(rays)
+    nb = rays.shape[1] // 9
+    mu = np.zeros(nb)
+    jac = np.zeros((4, nb))
+    _load().or_magnification(chi_s, nb, float(radius), _ptr(rays), _ptr(mu), _ptr(jac))
+    return mu, jac
+
+
+def mu_histogram(mu, n_bins: int = 200, log_lo: float = -0.1, log_hi: float = 0.3):
+    mu = _f64(mu)
+    pdf = np.zeros(n_bins)
+    mom = np.zeros(6)
+    rc = _load().or_mu_histogram(len(mu), _ptr(mu), n_bins, log_lo, log_hi, _ptr(pdf), _ptr(mom))
+    if rc != 0:
+        raise ValueError("or_mu_histogram failed")
+    return pdf, mom
