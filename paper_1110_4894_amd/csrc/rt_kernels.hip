@@ -1,0 +1,798 @@
+// gfx950 kernels of the ray-bundle lensing path.
+//
+// Method: Killedar, Lasky, Lewis & Fluke (2011).  The hot kernel is the
+// persistent trace kernel: every wavefront owns 64 rays (one per lane) and
+// integrates them through all RK4 steps; at every stage the rays' field is the
+// direct sum over the step's particle set (Sec. 3.3, eq. psi, derivs), streamed
+// in tiles through the wavefront's own LDS slice and read back as broadcasts.
+// Several wavefronts may share the same 64 rays and split the particles
+// between them, combining their partial sums through LDS.
+//
+// Design notes for CDNA4:
+//   * pair terms are plain VALU work (no MFMA: the sum is not a contraction);
+//     13 VALU ops per pair in FP32 plus one v_rsq on the transcendental unit;
+//   * the FP32 path works in a frame local to the wavefront: tiles are staged as
+//     particle - origin, and each lane holds its ray's offset from the origin,
+//     so FP32 differences stay well conditioned near the rays;
+//   * partial sums of each 16-particle sub-tile are added with Kahan
+//     compensation; FP64 is kept for the ray state and the integration;
+//   * work items (field, block of rays) are pulled from an atomic queue so that
+//     fields of very different particle counts share one launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int kKahanChunk = 32;     // particles summed plainly before a Kahan update
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+  float y = v - c;
+  float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// ---------------------------------------------------------------------------
+// Background: a(t) of eq. scalefac2 (t = lookback time) and da/dt.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scale_factor(const DevCosmo& c, double t, double& a, double& adot) {
+  const double rate = 1.5 * c.sqrt_ol * c.H0;
+  const double u = rate * (c.t0 - t);
+  const double e = exp(u);
+  const double ie = 1.0 / e;
+  const double sh = 0.5 * (e - ie), ch = 0.5 * (e + ie);
+  a = cbrt(c.ratio * sh * sh);
+  // a^3 = ratio sh^2  =>  3 a^2 da/dt = -2 ratio sh ch rate
+  adot = -(2.0 / 3.0) * rate * c.ratio * sh * ch / (a * a);
+}
+
+// ---------------------------------------------------------------------------
+// Uniform cuboid of unit density: U = int d^3x'/|p - x'| and dU/dp, from the
+// antiderivative of 1/R evaluated at the eight corners (mean-density term of
+// Sec. 3.3).  Each corner's three logarithms and three arctangents serve both
+// U and its gradient; terms whose coefficient vanishes are skipped, which
+// keeps faces, edges and corners finite (the observer sits on a face of the
+// first box replica).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double log_w_plus_r(double w, double R, double other2) {
+  if (other2 == 0.0) return 0.0;      // every coefficient of this log is zero then
+  return (w >= 0.0) ? log(w + R) : log(other2 / (R - w));
+}
+
+__device__ void cuboid_field(const double lo[3], const double hi[3], double px, double py, double pz, double& U,
+                             double& gx, double& gy, double& gz) {
+  U = gx = gy = gz = 0.0;
+  const double xs[2] = {lo[0] - px, hi[0] - px};
+  const double ys[2] = {lo[1] - py, hi[1] - py};
+  const double zs[2] = {lo[2] - pz, hi[2] - pz};
+#pragma unroll
+  for (int corner = 0; corner < 8; ++corner) {
+    const int i = corner & 1, j = (corner >> 1) & 1, k = (corner >> 2) & 1;
+    const double X = xs[i], Y = ys[j], Z = zs[k];
+    // sign = product over the axes of (+1 upper limit, -1 lower limit)
+    const double s = ((i + j + k) & 1) ? 1.0 : -1.0;
+    const double X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
+    const double R = sqrt(X2 + Y2 + Z2);
+    if (R == 0.0) continue;
+    const double LX = log_w_plus_r(X, R, Y2 + Z2);
+    const double LY = log_w_plus_r(Y, R, Z2 + X2);
+    const double LZ = log_w_plus_r(Z, R, X2 + Y2);
+    const double AX = (X != 0.0) ? atan(Y * Z / (X * R)) : 0.0;
+    const double AY = (Y != 0.0) ? atan(Z * X / (Y * R)) : 0.0;
+    const double AZ = (Z != 0.0) ? atan(X * Y / (Z * R)) : 0.0;
+    const double F = X * Y * LZ + Y * Z * LX + Z * X * LY - 0.5 * (X2 * AX + Y2 * AY + Z2 * AZ);
+    U += s * F;
+    // the limits move with p (d limit / dp = -1)
+    gx -= s * (Y * LZ + Z * LY - X * AX);
+    gy -= s * (Z * LX + X * LZ - Y * AY);
+    gz -= s * (X * LY + Y * LX - Z * AZ);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Geodesic right-hand side in z (Sec. 3.4 with x^3 as independent variable),
+// Christoffel symbols differentiated exactly from eq. expandingmetric with
+// psi = phi / a.  Y = (t, x, y, kt, kx, ky, kz).
+// ---------------------------------------------------------------------------
+struct State {
+  double t, x, y, kt, kx, ky, kz;
+};
+
+__device__ __forceinline__ State rhs(const DevCosmo& c, const State& Y, double phi, double gx, double gy, double gz,
+                                     double& a_out) {
+  double a, adot;
+  scale_factor(c, Y.t, a, adot);
+  a_out = a;
+  const double inv_a = 1.0 / a;
+  const double invE = 1.0 / (1.0 + 2.0 * phi * inv_a);
+  const double invF = 1.0 / (a * a - 2.0 * a * phi);
+  const double gk = gx * Y.kx + gy * Y.ky + gz * Y.kz;
+  const double k2 = Y.kx * Y.kx + Y.ky * Y.ky + Y.kz * Y.kz;
+  const double kt2 = Y.kt * Y.kt;
+  const double hub = adot * (a - phi);
+  const double At = (-adot * phi * inv_a * inv_a * kt2 + 2.0 * Y.kt * inv_a * gk + hub * k2) * invE;
+  const double c1 = kt2 * inv_a, c2 = 2.0 * hub * Y.kt;
+  const double Ax = (gx * c1 + c2 * Y.kx + a * (gx * k2 - 2.0 * Y.kx * gk)) * invF;
+  const double Ay = (gy * c1 + c2 * Y.ky + a * (gy * k2 - 2.0 * Y.ky * gk)) * invF;
+  const double Az = (gz * c1 + c2 * Y.kz + a * (gz * k2 - 2.0 * Y.kz * gk)) * invF;
+  const double iz = 1.0 / Y.kz;
+  return State{Y.kt * iz, Y.kx * iz, Y.ky * iz, -At * iz, -Ax * iz, -Ay * iz, -Az * iz};
+}
+
+__device__ __forceinline__ State axpy(const State& Y, double h, const State& k) {
+  return State{Y.t + h * k.t, Y.x + h * k.x, Y.y + h * k.y, Y.kt + h * k.kt, Y.kx + h * k.kx, Y.ky + h * k.ky,
+               Y.kz + h * k.kz};
+}
+
+// ---------------------------------------------------------------------------
+// Field sums over one wavefront's share of a particle set.
+//
+// A wavefront holds 7 whole bundles: lane l < 63 owns ray l of the group
+// (bundle l / 9, ray l % 9 of it, the anchor first); lane 63 only helps.
+// Raw sums returned: S0 = sum m / r,  S = sum m (x_j - x) / r^3.
+// ---------------------------------------------------------------------------
+constexpr int kLanes = 63;              // rays per wavefront
+constexpr int kSeg = 7;                 // bundles per wavefront
+constexpr int kTile32 = 64;             // particles per FP32 tile (one per lane)
+constexpr int kCopyStride = kTile32 + 1;  // float4 per bundle copy (+1 spreads the copies over LDS banks)
+
+__device__ __forceinline__ int lane_segment(int lane) { return lane < kLanes ? lane / 9 : kSeg - 1; }
+
+// FP32 path.  Each tile of 64 particles is staged once per bundle of the
+// wavefront, as particle - anchor (7 copies); each lane then subtracts only its
+// ray's small offset from its anchor.  The anchor-relative part is rounded
+// identically for the 9 rays of a bundle, so the differences between ring rays
+// and anchor that carry the lensing signal keep full FP32 resolution wherever
+// the bundles are on the sky.
+template <int WPR>
+__device__ __forceinline__ void sum_fp32(const DevSet& s, float4* tile, int q, int lane, const float (&A)[kSeg][3],
+                                         float rx, float ry, float rz, double& S0, double& Sx, double& Sy,
+                                         double& Sz) {
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+  const int64_t n = s.n;
+  const float e2 = s.eps2f;
+  const int64_t n_chunks = (n + kTile32 - 1) / kTile32;
+  const float4* __restrict__ src = s.p32;
+  const float4* mine = tile + lane_segment(lane) * kCopyStride;
+  for (int64_t ch = q; ch < n_chunks; ch += WPR) {
+    const int64_t j = ch * kTile32 + lane;
+    const float4 p = (j < n) ? src[j] : make_float4(1e15f, 1e15f, 1e15f, 0.f);
+#pragma unroll
+    for (int b = 0; b < kSeg; ++b)
+      tile[b * kCopyStride + lane] = make_float4(p.x - A[b][0], p.y - A[b][1], p.z - A[b][2], p.w);
+    wave_sync();
+#pragma unroll 1
+    for (int k0 = 0; k0 < kTile32; k0 += kKahanChunk) {
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+      for (int u = 0; u < kKahanChunk; ++u) {
+        const float4 c = mine[k0 + u];
+        const float ex = c.x - rx, ey = c.y - ry, ez = c.z - rz;
+        float r2 = fmaf(ex, ex, e2);
+        r2 = fmaf(ey, ey, r2);
+        r2 = fmaf(ez, ez, r2);
+        const float ri = __builtin_amdgcn_rsqf(r2);
+        const float mr = c.w * ri;
+        p0 += mr;
+        const float mr3 = mr * ri * ri;
+        p1 = fmaf(mr3, ex, p1);
+        p2 = fmaf(mr3, ey, p2);
+        p3 = fmaf(mr3, ez, p3);
+      }
+      kahan_add(s0, c0, p0);
+      kahan_add(s1, c1, p1);
+      kahan_add(s2, c2, p2);
+      kahan_add(s3, c3, p3);
+    }
+    wave_sync();
+  }
+  S0 = (double)s0 - (double)c0;
+  Sx = (double)s1 - (double)c1;
+  Sy = (double)s2 - (double)c2;
+  Sz = (double)s3 - (double)c3;
+}
+
+// FP64 path: tiles of the caller's FP64 particles, broadcast to every lane.
+template <int T, int WPR>
+__device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, int lane, double x, double y,
+                                         double z, double& S0, double& Sx, double& Sy, double& Sz) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int64_t n = s.n;
+  const double e2 = s.eps2;
+  const int64_t n_chunks = (n + T - 1) / T;
+  const double* __restrict__ px = s.p64;
+  for (int64_t ch = q; ch < n_chunks; ch += WPR) {
+    const int64_t base = ch * T;
+#pragma unroll
+    for (int k = lane; k < T; k += 64) {
+      const int64_t j = base + k;
+      tile[k] = (j < n) ? make_double4(px[j], px[n + j], px[2 * n + j], px[3 * n + j])
+                        : make_double4(1e100, 1e100, 1e100, 0.0);
+    }
+    wave_sync();
+#pragma unroll 8
+    for (int k = 0; k < T; ++k) {
+      const double4 c = tile[k];
+      const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
+      double r2 = fma(ex, ex, e2);
+      r2 = fma(ey, ey, r2);
+      r2 = fma(ez, ez, r2);
+      const double ri = rsqrt(r2);
+      const double mr = c.w * ri;
+      a0 += mr;
+      const double mr3 = mr * ri * ri;
+      a1 = fma(mr3, ex, a1);
+      a2 = fma(mr3, ey, a2);
+      a3 = fma(mr3, ez, a3);
+    }
+    wave_sync();
+  }
+  S0 = a0;
+  Sx = a1;
+  Sy = a2;
+  Sz = a3;
+}
+
+// LDS needed by one wavefront's tiles.
+template <bool F64, int T>
+struct TileSpace {
+  static constexpr int kElems = F64 ? T : kSeg * kCopyStride;
+  using Elem = typename std::conditional<F64, double4, float4>::type;
+};
+
+// Field of one set at the lane's point for a group of WPR wavefronts holding
+// the same rays: each sums its share of the tiles and the shares meet in LDS
+// in a fixed order, so every wavefront of the group gets identical results.
+template <bool F64, int T, int WPR>
+struct FieldEval {
+  using Tile = typename TileSpace<F64, T>::Elem;
+
+  __device__ static void eval(const DevCosmo& c, const DevSet& s, Tile* tile, double* red, int q, int lane, double x,
+                              double y, double z, double& phi, double& gx, double& gy, double& gz) {
+    double S0, Sx, Sy, Sz;
+    if constexpr (F64) {
+      sum_fp64<T, WPR>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
+    } else {
+      // positions in the set's frame (FP64), each bundle's anchor rounded to FP32
+      const double X = x - s.org[0], Yv = y - s.org[1], Z = z - s.org[2];
+      const int anchor = 9 * lane_segment(lane);
+      const double AX = __shfl(X, anchor), AY = __shfl(Yv, anchor), AZ = __shfl(Z, anchor);
+      const float ax = (float)AX, ay = (float)AY, az = (float)AZ;
+      float A[kSeg][3];
+#pragma unroll
+      for (int b = 0; b < kSeg; ++b) {
+        A[b][0] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), 9 * b));
+        A[b][1] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), 9 * b));
+        A[b][2] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), 9 * b));
+      }
+      const float rx = (float)(X - (double)ax), ry = (float)(Yv - (double)ay), rz = (float)(Z - (double)az);
+      sum_fp32<WPR>(s, tile, q, lane, A, rx, ry, rz, S0, Sx, Sy, Sz);
+    }
+    if constexpr (WPR > 1) {
+      // red: [WPR][4][64] for this group
+      red[(q * 4 + 0) * 64 + lane] = S0;
+      red[(q * 4 + 1) * 64 + lane] = Sx;
+      red[(q * 4 + 2) * 64 + lane] = Sy;
+      red[(q * 4 + 3) * 64 + lane] = Sz;
+      __syncthreads();
+      S0 = Sx = Sy = Sz = 0.0;
+#pragma unroll
+      for (int w = 0; w < WPR; ++w) {
+        S0 += red[(w * 4 + 0) * 64 + lane];
+        Sx += red[(w * 4 + 1) * 64 + lane];
+        Sy += red[(w * 4 + 2) * 64 + lane];
+        Sz += red[(w * 4 + 3) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    phi = -c.G * S0;
+    gx = -c.G * Sx;
+    gy = -c.G * Sy;
+    gz = -c.G * Sz;
+    if (s.background) {
+      double U, ux, uy, uz;
+      cuboid_field(s.lo, s.hi, x, y, z, U, ux, uy, uz);
+      phi += c.G_rho * U;
+      gx += c.G_rho * ux;
+      gy += c.G_rho * uy;
+      gz += c.G_rho * uz;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The persistent trace kernel.
+// NW wavefronts per workgroup; WPR of them share 63 rays (7 bundles) and split
+// the particles; T particles per FP64 tile.  Four wavefronts per SIMD are
+// requested: the FP64 state stays in registers through the pair loop, and
+// the compiler spills only inside the rarely used cuboid-background code.
+// ---------------------------------------------------------------------------
+template <bool F64, int NW, int WPR, int T>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void trace_kernel(TraceParams P) {
+  constexpr int NG = NW / WPR;
+  using FE = FieldEval<F64, T, WPR>;
+  using Tile = typename FE::Tile;
+  __shared__ Tile tiles[NW][TileSpace<F64, T>::kElems];
+  __shared__ double red[NG][WPR > 1 ? WPR * 4 * 64 : 1];
+  __shared__ int s_item;
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = wave / WPR, q = wave % WPR;
+  const DevCosmo& cz = P.cosmo;
+
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(P.queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= P.n_items) break;
+
+    const WorkItem wi = P.items[item];
+    const DevField f = P.fields[wi.field];
+    const int64_t rend = f.ray_begin + f.n_rays;
+    int64_t ri = f.ray_begin + (int64_t)wi.block * (kLanes * NG) + g * kLanes + (lane < kLanes ? lane : kLanes - 1);
+    const bool valid = lane < kLanes && ri < rend;
+    if (ri >= rend) ri = rend - 1;
+    const int64_t N = P.n_rays;
+    State Y{P.rays[ri], P.rays[N + ri], P.rays[2 * N + ri], P.rays[4 * N + ri], P.rays[5 * N + ri],
+            P.rays[6 * N + ri], P.rays[7 * N + ri]};
+    double zpos = P.rays[3 * N + ri];
+    uint8_t flag = 0;
+    bool live = true;
+    const int sb = P.step_begin < 0 ? 0 : P.step_begin;
+    const int se = P.step_end > f.n_steps ? f.n_steps : P.step_end;
+
+    for (int s = sb; s < se; ++s) {
+      const double Z0 = P.nodes[f.node_off + s], Z1 = P.nodes[f.node_off + s + 1];
+      const double h = Z1 - Z0, hh = 0.5 * h;
+      const int S = P.step_set[f.step_off + s];
+      State acc, Ys, k;
+      double a;
+#pragma unroll 1
+      for (int stage = 0; stage < 4; ++stage) {
+        const State& Yin = (stage == 0) ? Y : Ys;
+        const double zs = (stage == 0) ? Z0 : ((stage == 3) ? Z1 : Z0 + hh);
+        double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        if (S >= 0) {
+          const DevSet& set = P.sets[f.set_off + S];
+          FE::eval(cz, set, tiles[wave], red[g], q, lane, Yin.x, Yin.y, zs, phi, gx, gy, gz);
+        }
+        k = rhs(cz, Yin, phi, gx, gy, gz, a);
+        if (stage == 0) {
+          if (fabs(phi) / a > 1e-2) flag |= 4;
+          acc = k;
+          Ys = axpy(Y, hh, k);
+        } else if (stage == 1) {
+          acc = axpy(acc, 2.0, k);
+          Ys = axpy(Y, hh, k);
+        } else if (stage == 2) {
+          acc = axpy(acc, 2.0, k);
+          Ys = axpy(Y, h, k);
+        } else {
+          acc = axpy(acc, 1.0, k);
+        }
+      }
+      if (live) {
+        const State Yn = axpy(Y, h / 6.0, acc);
+        const bool finite = isfinite(Yn.t) && isfinite(Yn.x) && isfinite(Yn.y) && isfinite(Yn.kt) &&
+                            isfinite(Yn.kx) && isfinite(Yn.ky) && isfinite(Yn.kz);
+        if (!finite) {
+          flag |= 1;
+          live = false;
+        } else if (!(Yn.kz > 0.0)) {
+          flag |= 2;
+          live = false;
+        } else {
+          Y = Yn;
+          zpos = Z1;
+        }
+      }
+    }
+    if (valid) {
+      P.rays[ri] = Y.t;
+      P.rays[N + ri] = Y.x;
+      P.rays[2 * N + ri] = Y.y;
+      P.rays[3 * N + ri] = zpos;
+      P.rays[4 * N + ri] = Y.kt;
+      P.rays[5 * N + ri] = Y.kx;
+      P.rays[6 * N + ri] = Y.ky;
+      P.rays[7 * N + ri] = Y.kz;
+      if (P.flags && flag) P.flags[ri] |= flag;
+    }
+  }
+}
+
+// Field at arbitrary points: one wavefront = 63 points, no particle split.
+// In the FP32 path every group of 9 consecutive points shares the frame of its
+// first point, as the rays of a bundle do in the trace kernel.
+template <bool F64, int T>
+__global__ __launch_bounds__(256) void field_eval_kernel(DevCosmo c, const DevSet* set_p, int64_t n,
+                                                         const double* pts, double* phi, double* grad) {
+  using FE = FieldEval<F64, T, 1>;
+  using Tile = typename FE::Tile;
+  __shared__ Tile tiles[4][TileSpace<F64, T>::kElems];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * kLanes;
+  if (w0 >= n) return;   // whole wavefront idle
+  int64_t i = w0 + (lane < kLanes ? lane : kLanes - 1);
+  const bool valid = lane < kLanes && i < n;
+  if (i >= n) i = n - 1;
+  const DevSet set = *set_p;
+  double p, gx, gy, gz;
+  FE::eval(c, set, tiles[wave], nullptr, 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx, gy, gz);
+  if (valid) {
+    phi[i] = p;
+    grad[i] = gx;
+    grad[n + i] = gy;
+    grad[2 * n + i] = gz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels: queue reset, set frames, FP32 copies.
+// ---------------------------------------------------------------------------
+__global__ void reset_queue_kernel(int32_t* q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+}
+
+// Frame origin of each set: the cuboid centre for sets with a background,
+// otherwise the first particle.
+__global__ void prepare_sets_kernel(DevSet* sets, int32_t n_sets) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sets) return;
+  DevSet& s = sets[i];
+  if (s.background) {
+    for (int d = 0; d < 3; ++d) s.org[d] = 0.5 * (s.lo[d] + s.hi[d]);
+  } else if (s.n > 0) {
+    for (int d = 0; d < 3; ++d) s.org[d] = s.p64[d * s.n];
+  } else {
+    for (int d = 0; d < 3; ++d) s.org[d] = 0.0;
+  }
+}
+
+__global__ void convert_set_kernel(const DevSet* set, const double* p64, float4* p32, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double ox = set->org[0], oy = set->org[1], oz = set->org[2];
+  p32[j] = make_float4((float)(p64[j] - ox), (float)(p64[n + j] - oy), (float)(p64[2 * n + j] - oz),
+                       (float)p64[3 * n + j]);
+}
+
+// ---------------------------------------------------------------------------
+// Bundle construction (Sec. 2.4, 3.1): one thread per ray.
+// ---------------------------------------------------------------------------
+__constant__ double kRingCos[8] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
+                                   -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440};
+__constant__ double kRingSin[8] = {0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440,
+                                   0.0, -0.70710678118654752440, -1.0, -0.70710678118654752440};
+
+__global__ void bundles_kernel(DevCosmo c, const double* phi_obs, int64_t b0, int64_t nb_range, int64_t n_bundles,
+                               const double* theta, double radius, double* rays) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 9 * nb_range) return;
+  const int64_t b = b0 + i / 9;
+  const int k = (int)(i % 9);
+  double tx = theta[b], ty = theta[n_bundles + b];
+  if (k > 0) {
+    tx += radius * kRingCos[k - 1];
+    ty += radius * kRingSin[k - 1];
+  }
+  double a0, adot0;
+  scale_factor(c, 0.0, a0, adot0);
+  const double ph = phi_obs ? *phi_obs : 0.0;
+  const double E0 = 1.0 + 2.0 * ph / a0, F0 = a0 * a0 - 2.0 * a0 * ph;
+  const double norm = sqrt(E0 / F0) / sqrt(tx * tx + ty * ty + 1.0);
+  const int64_t N = 9 * n_bundles, r = 9 * b + k;
+  rays[r] = 0.0;
+  rays[N + r] = 0.0;
+  rays[2 * N + r] = 0.0;
+  rays[3 * N + r] = 0.0;
+  rays[4 * N + r] = 1.0;
+  rays[5 * N + r] = norm * tx;
+  rays[6 * N + r] = norm * ty;
+  rays[7 * N + r] = norm;
+}
+
+// ---------------------------------------------------------------------------
+// Bundle reduction (Sec. 2.4, eq. lensmap, magnification): 9 consecutive lanes
+// hold one bundle (7 bundles per wavefront, lane 63 idle); offsets from the
+// anchor and the neighbour's offsets arrive by lane shuffles, and the five
+// sums are reduced within each 9-lane segment.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void magnification_kernel(double chi_s, int64_t nb, double radius, const double* rays,
+                                                            double* mu, double* jac) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int seg = lane / 9, k = lane % 9;
+  const int64_t b = ((int64_t)blockIdx.x * 4 + wave) * 7 + seg;
+  const bool valid = (seg < 7) && (b < nb);
+  const int64_t N = 9 * nb;
+  const int64_t r = valid ? 9 * b + k : 0;
+  const double x = rays[N + r], y = rays[2 * N + r];
+  const int anchor = seg * 9;
+  const double dx = x - __shfl(x, anchor), dy = y - __shfl(y, anchor);
+  const int nxt = anchor + (k == 8 ? 1 : k + 1);
+  const double dxn = __shfl(dx, nxt), dyn = __shfl(dy, nxt);
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (k > 0) {
+    const double ux = radius * kRingCos[k - 1], uy = radius * kRingSin[k - 1];
+    v[0] = 0.5 * (dx * dyn - dy * dxn);
+    v[1] = dx * ux;
+    v[2] = dx * uy;
+    v[3] = dy * ux;
+    v[4] = dy * uy;
+  }
+#pragma unroll
+  for (int off = 1; off < 9; off <<= 1) {
+    const int src = (k + off < 9) ? lane + off : lane;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const double o = __shfl(v[m], src);
+      if (k + off < 9) v[m] += o;
+    }
+  }
+  if (valid && k == 0) {
+    const double hom = 2.0 * sqrt(2.0) * radius * radius * chi_s * chi_s;
+    mu[b] = hom / v[0];
+    if (jac) {
+      const double nrm = 1.0 / (4.0 * radius * radius * chi_s);
+      const double a11 = v[1] * nrm, a12 = v[2] * nrm, a21 = v[3] * nrm, a22 = v[4] * nrm;
+      jac[b] = 1.0 - 0.5 * (a11 + a22);
+      jac[nb + b] = 0.5 * (a22 - a11);
+      jac[2 * nb + b] = -0.5 * (a12 + a21);
+      jac[3 * nb + b] = 0.5 * (a21 - a12);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Source-weighted mu histogram (Sec. 5.3, eq. weighthisto), deterministic:
+// every sum runs in a fixed order (strided per thread, then a tree in LDS).
+// work layout: [n_bins] bin weights, then sum w, sum w mu, n_bad, n_under, n_over.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int mu_bin(double m, double lo, double hi, int nb) {
+  const double lm = log10(m);
+  if (lm < lo) return -1;
+  if (lm >= hi) return nb;
+  int i = (int)floor((lm - lo) / (hi - lo) * nb);
+  return i >= nb ? nb - 1 : i;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void hist_bins_kernel(int64_t n, const double* mu, int32_t nb, double lo, double hi,
+                                                        double* work) {
+  __shared__ double sh[256];
+  const int bin = blockIdx.x;
+  if (bin < nb) {
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      const double m = mu[i];
+      if (m > 0.0 && mu_bin(m, lo, hi, nb) == bin) acc += 1.0 / m;
+    }
+    const double t = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) work[bin] = t;
+  } else {
+    double sw = 0.0, swm = 0.0, bad = 0.0, under = 0.0, over = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      const double m = mu[i];
+      if (!(m > 0.0)) {
+        bad += 1.0;
+        continue;
+      }
+      const double w = 1.0 / m;
+      sw += w;
+      swm += w * m;
+      const int b = mu_bin(m, lo, hi, nb);
+      if (b < 0) under += 1.0;
+      if (b >= nb) over += 1.0;
+    }
+    const double t0 = block_sum<256>(sw, sh), t1 = block_sum<256>(swm, sh), t2 = block_sum<256>(bad, sh);
+    const double t3 = block_sum<256>(under, sh), t4 = block_sum<256>(over, sh);
+    if (threadIdx.x == 0) {
+      work[nb] = t0;
+      work[nb + 1] = t1;
+      work[nb + 2] = t2;
+      work[nb + 3] = t3;
+      work[nb + 4] = t4;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void hist_final_kernel(int64_t n, const double* mu, int32_t nb, double lo, double hi,
+                                                         const double* work, double* pdf, double* moments) {
+  __shared__ double sh[256];
+  const double sw = work[nb];
+  const double mean = sw > 0.0 ? work[nb + 1] / sw : 0.0;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double m = mu[i];
+    if (m > 0.0) acc += (1.0 / m) * (m - mean) * (m - mean);
+  }
+  const double var = block_sum<256>(acc, sh);
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    const double e0 = lo + (hi - lo) * i / nb, e1 = lo + (hi - lo) * (i + 1) / nb;
+    const double width = pow(10.0, e1) - pow(10.0, e0);
+    pdf[i] = sw > 0.0 ? work[i] / (sw * width) : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    moments[0] = sw;
+    moments[1] = mean;
+    moments[2] = sw > 0.0 ? sqrt(var / sw) : 0.0;
+    moments[3] = work[nb + 2];
+    moments[4] = work[nb + 3];
+    moments[5] = work[nb + 4];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plan table.
+// ---------------------------------------------------------------------------
+struct PlanShape {
+  int nw, wpr, tile;
+};
+
+constexpr PlanShape kPlans32[] = {{8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {8, 8, 64}, {4, 1, 64}, {4, 4, 64}};
+constexpr PlanShape kPlans64[] = {{8, 1, 128}, {8, 2, 128}, {8, 4, 128}, {8, 8, 64}, {4, 1, 128}, {4, 4, 128}};
+constexpr int kNumPlans = 6;
+
+template <bool F64, int I>
+struct PlanKernel;
+
+#define RT_PLAN(F64, I, TABLE)                                                                   \
+  template <>                                                                                    \
+  struct PlanKernel<F64, I> {                                                                    \
+    static constexpr PlanShape S = TABLE[I];                                                     \
+    static const void* fn() { return (const void*)&trace_kernel<F64, S.nw, S.wpr, S.tile>; }      \
+    static hipError_t launch(const TraceParams& p, int grid, hipStream_t st) {                  \
+      hipLaunchKernelGGL((trace_kernel<F64, S.nw, S.wpr, S.tile>), dim3(grid), dim3(S.nw * 64), 0, st, p); \
+      return hipGetLastError();                                                                  \
+    }                                                                                            \
+  };
+
+RT_PLAN(false, 0, kPlans32)
+RT_PLAN(false, 1, kPlans32)
+RT_PLAN(false, 2, kPlans32)
+RT_PLAN(false, 3, kPlans32)
+RT_PLAN(false, 4, kPlans32)
+RT_PLAN(false, 5, kPlans32)
+RT_PLAN(true, 0, kPlans64)
+RT_PLAN(true, 1, kPlans64)
+RT_PLAN(true, 2, kPlans64)
+RT_PLAN(true, 3, kPlans64)
+RT_PLAN(true, 4, kPlans64)
+RT_PLAN(true, 5, kPlans64)
+#undef RT_PLAN
+
+template <bool F64>
+const void* plan_fn(int id) {
+  switch (id) {
+    case 0: return PlanKernel<F64, 0>::fn();
+    case 1: return PlanKernel<F64, 1>::fn();
+    case 2: return PlanKernel<F64, 2>::fn();
+    case 3: return PlanKernel<F64, 3>::fn();
+    case 4: return PlanKernel<F64, 4>::fn();
+    default: return PlanKernel<F64, 5>::fn();
+  }
+}
+
+template <bool F64>
+hipError_t plan_launch(int id, const TraceParams& p, int grid, hipStream_t st) {
+  switch (id) {
+    case 0: return PlanKernel<F64, 0>::launch(p, grid, st);
+    case 1: return PlanKernel<F64, 1>::launch(p, grid, st);
+    case 2: return PlanKernel<F64, 2>::launch(p, grid, st);
+    case 3: return PlanKernel<F64, 3>::launch(p, grid, st);
+    case 4: return PlanKernel<F64, 4>::launch(p, grid, st);
+    default: return PlanKernel<F64, 5>::launch(p, grid, st);
+  }
+}
+
+}  // namespace
+
+int plan_count(bool) { return kNumPlans; }
+
+rt_plan_info plan_info(bool fp64, int id) {
+  const PlanShape s = fp64 ? kPlans64[id] : kPlans32[id];
+  rt_plan_info r;
+  r.waves_per_block = s.nw;
+  r.waves_per_group = s.wpr;
+  r.tile = s.tile;
+  r.rays_per_block = kLanes * s.nw / s.wpr;
+  return r;
+}
+
+hipError_t plan_occupancy(bool fp64, int id, int* blocks_per_cu) {
+  const PlanShape s = fp64 ? kPlans64[id] : kPlans32[id];
+  const void* fn = fp64 ? plan_fn<true>(id) : plan_fn<false>(id);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, s.nw * 64, 0);
+}
+
+hipError_t launch_trace(bool fp64, int id, const TraceParams& p, int grid, hipStream_t s) {
+  return fp64 ? plan_launch<true>(id, p, grid, s) : plan_launch<false>(id, p, grid, s);
+}
+
+hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_sets(DevSet* sets, int32_t n_sets, hipStream_t s) {
+  if (n_sets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prepare_sets_kernel, dim3((n_sets + 63) / 64), dim3(64), 0, s, sets, n_sets);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_set(const DevSet* set_dev, const double* p64, float4* p32, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(convert_set_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, set_dev, p64, p32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bundles(DevCosmo c, const double* phi_obs, int64_t b0, int64_t nb_range, int64_t n_bundles,
+                          const double* theta, double radius, double* rays, hipStream_t s) {
+  if (nb_range <= 0) return hipSuccess;
+  const int64_t n = 9 * nb_range;
+  hipLaunchKernelGGL(bundles_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c, phi_obs, b0, nb_range,
+                     n_bundles, theta, radius, rays);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_eval(DevCosmo c, const DevSet* set, bool fp64, int64_t n, const double* pts, double* phi,
+                             double* grad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 4 * kLanes - 1) / (4 * kLanes));
+  if (fp64)
+    hipLaunchKernelGGL((field_eval_kernel<true, kPlans64[0].tile>), dim3(grid), dim3(256), 0, s, c, set, n, pts, phi,
+                       grad);
+  else
+    hipLaunchKernelGGL((field_eval_kernel<false, kPlans32[0].tile>), dim3(grid), dim3(256), 0, s, c, set, n, pts,
+                       phi, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const double* rays, double* mu,
+                                double* jac, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  const int64_t waves = (nb + 6) / 7;
+  hipLaunchKernelGGL(magnification_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, chi_s, nb, radius,
+                     rays, mu, jac);
+  return hipGetLastError();
+}
+
+hipError_t launch_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi, double* pdf,
+                            double* moments, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(hist_bins_kernel, dim3(n_bins + 1), dim3(256), 0, s, n, mu, n_bins, log_lo, log_hi, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hist_final_kernel, dim3(1), dim3(256), 0, s, n, mu, n_bins, log_lo, log_hi, work, pdf, moments);
+  return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,260 @@
+"""ctypes binding of librt.so (include/rt.h): same names, argument marshalling only.
+
+Device arrays are passed as torch CUDA tensors (or raw integer device
+addresses); every step of the lensing path runs in the library's HIP kernels.
+There is no CPU fallback: if librt.so is missing or cannot be loaded, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt.so")
+
+RT_OK = 0
+RT_FP64 = 0
+RT_FP32_KAHAN = 1
+PRECISIONS = {"fp64": RT_FP64, "fp32k": RT_FP32_KAHAN}
+
+FLAG_NONFINITE = 1
+FLAG_TURNED_BACK = 2
+FLAG_STRONG_FIELD = 4
+
+
+class RTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("rt status %d: %s" % (status, message))
+        self.status = status
+
+
+class rt_cosmology(C.Structure):
+    _fields_ = [("omega_m", C.c_double), ("omega_lambda", C.c_double), ("h", C.c_double)]
+
+
+class rt_particle_set(C.Structure):
+    _fields_ = [("n", C.c_int64), ("xyzm", C.c_void_p), ("softening", C.c_double), ("background", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class rt_field(C.Structure):
+    _fields_ = [("n_sets", C.c_int32), ("sets", C.c_void_p), ("n_steps", C.c_int32), ("z_nodes", C.c_void_p),
+                ("step_set", C.c_void_p), ("bundle_offset", C.c_int64), ("n_bundles", C.c_int64)]
+
+
+class rt_plan_info(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("waves_per_group", C.c_int32), ("tile", C.c_int32),
+                ("rays_per_block", C.c_int32)]
+
+
+class rt_trace_info(C.Structure):
+    _fields_ = [("kernel_ms", C.c_double), ("interactions", C.c_double), ("plan_id", C.c_int32),
+                ("grid_blocks", C.c_int32), ("n_items", C.c_int32), ("graph_reused", C.c_int32)]
+
+
+EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
+           "rt_magnification", "rt_mu_histogram", "rt_field_eval", "rt_plan_count", "rt_plan_describe",
+           "rt_force_plan", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
+           "rt_release_caches"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librt.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("librt.so not found at %s; build it with `python -m paper_1110_4894_amd.build`" % path)
+    lib = C.CDLL(path)
+    d, p, i32, i64, st = C.c_double, C.c_void_p, C.c_int32, C.c_int64, C.c_int
+    sigs = {
+        "rt_comoving_distance": (st, [p, d, p]),
+        "rt_make_schedule": (st, [d, d, d, i32, d, p, i32, p]),
+        "rt_replica_step_sets": (st, [p, i32, d, i32, p]),
+        "rt_build_bundles": (st, [p, p, i32, i64, p, d, p, p]),
+        "rt_trace": (st, [p, d, p, i32, st, i32, i32, i64, p, p, p]),
+        "rt_magnification": (st, [p, d, i64, d, p, p, p, p]),
+        "rt_mu_histogram": (st, [i64, p, i32, d, d, p, p, p]),
+        "rt_field_eval": (st, [p, p, st, i64, p, p, p, p]),
+        "rt_plan_count": (i32, [st]),
+        "rt_plan_describe": (st, [st, i32, p]),
+        "rt_force_plan": (st, [st, i32]),
+        "rt_autotune": (st, [p, d, p, i32, st, i32, i32, i64, p, p, p]),
+        "rt_enable_timing": (st, [i32]),
+        "rt_last_trace_info": (st, [p]),
+        "rt_last_error": (C.c_char_p, []),
+        "rt_release_caches": (None, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != RT_OK:
+        raise RTError(status, load().rt_last_error().decode())
+
+
+def _dptr(x) -> Optional[int]:
+    """Device address of a torch tensor (or an int address), None for None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def cosmology(omega_m: float = 0.3, omega_lambda: float = 0.7, h: float = 0.7) -> rt_cosmology:
+    return rt_cosmology(omega_m, omega_lambda, h)
+
+
+# ----------------------------------------------------------------------------- field tables
+class FieldTable:
+    """Owns the host-side rt_field / rt_particle_set arrays (and keeps alive the
+    arrays they point to).  `sets_per_field[f]` lists (xyzm_tensor [4, n] float64
+    on the device, softening, background, lo, hi)."""
+
+    def __init__(self, fields: Sequence[dict]):
+        self._keep = []
+        self.arr = (rt_field * max(1, len(fields)))()
+        for i, f in enumerate(fields):
+            sets = (rt_particle_set * max(1, len(f["sets"])))()
+            for j, s in enumerate(f["sets"]):
+                xyzm = s["xyzm"]
+                n = int(xyzm.shape[1]) if xyzm is not None else 0
+                sets[j] = rt_particle_set(n, _dptr(xyzm) if n else None, float(s.get("softening", 0.0)),
+                                          1 if s.get("background") else 0,
+                                          (C.c_double * 3)(*s.get("lo", (0.0, 0.0, 0.0))),
+                                          (C.c_double * 3)(*s.get("hi", (0.0, 0.0, 0.0))))
+                self._keep.append(xyzm)
+            nodes = np.ascontiguousarray(f["z_nodes"], dtype=np.float64)
+            ss = np.ascontiguousarray(f["step_set"], dtype=np.int32)
+            self._keep += [sets, nodes, ss]
+            self.arr[i] = rt_field(len(f["sets"]), C.addressof(sets), len(nodes) - 1, nodes.ctypes.data,
+                                   ss.ctypes.data, int(f["bundle_offset"]), int(f["n_bundles"]))
+        self.n = len(fields)
+
+    @property
+    def ptr(self) -> int:
+        return C.addressof(self.arr)
+
+
+def make_particle_set(xyzm, softening: float = 0.0, background: bool = False, lo=(0, 0, 0), hi=(0, 0, 0)):
+    n = int(xyzm.shape[1]) if xyzm is not None else 0
+    s = rt_particle_set(n, _dptr(xyzm) if n else None, float(softening), 1 if background else 0,
+                        (C.c_double * 3)(*lo), (C.c_double * 3)(*hi))
+    s._keep = xyzm
+    return s
+
+
+# ----------------------------------------------------------------------------- entry points
+def rt_comoving_distance(cosmo: rt_cosmology, z: float) -> float:
+    out = C.c_double()
+    _check(load().rt_comoving_distance(C.byref(cosmo), float(z), C.addressof(out)))
+    return out.value
+
+
+def rt_make_schedule(chi_s: float, z_lo: float, z_hi: float, n_fine: int, q: float, capacity: int = 1 << 20):
+    nodes = np.zeros(capacity)
+    n = C.c_int32()
+    _check(load().rt_make_schedule(float(chi_s), float(z_lo), float(z_hi), int(n_fine), float(q), nodes.ctypes.data,
+                                   int(capacity), C.addressof(n)))
+    return nodes[: n.value + 1].copy()
+
+
+def rt_replica_step_sets(nodes, box: float, n_replicas: int):
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    out = np.zeros(len(nodes) - 1, dtype=np.int32)
+    _check(load().rt_replica_step_sets(nodes.ctypes.data, len(nodes) - 1, float(box), int(n_replicas),
+                                       out.ctypes.data))
+    return out
+
+
+def rt_build_bundles(cosmo, table: FieldTable, n_bundles: int, theta, radius: float, rays, stream=None):
+    _check(load().rt_build_bundles(C.byref(cosmo), table.ptr if table.n else None, table.n, int(n_bundles),
+                                   _dptr(theta), float(radius), _dptr(rays), _stream(stream)))
+
+
+def rt_trace(cosmo, z_source: float, table: FieldTable, precision: int, step_begin: int, step_end: int,
+             n_bundles: int, rays, flags=None, stream=None):
+    _check(load().rt_trace(C.byref(cosmo), float(z_source), table.ptr if table.n else None, table.n,
+                           int(precision), int(step_begin), int(step_end), int(n_bundles), _dptr(rays),
+                           _dptr(flags), _stream(stream)))
+
+
+def rt_magnification(cosmo, z_source: float, n_bundles: int, radius: float, rays, mu, jac=None, stream=None):
+    _check(load().rt_magnification(C.byref(cosmo), float(z_source), int(n_bundles), float(radius), _dptr(rays),
+                                   _dptr(mu), _dptr(jac), _stream(stream)))
+
+
+def rt_mu_histogram(n: int, mu, n_bins: int, log_lo: float, log_hi: float, pdf, moments, stream=None):
+    _check(load().rt_mu_histogram(int(n), _dptr(mu), int(n_bins), float(log_lo), float(log_hi), _dptr(pdf),
+                                  _dptr(moments), _stream(stream)))
+
+
+def rt_field_eval(cosmo, pset: rt_particle_set, precision: int, n: int, points, phi, grad, stream=None):
+    _check(load().rt_field_eval(C.byref(cosmo), C.byref(pset), int(precision), int(n), _dptr(points), _dptr(phi),
+                                _dptr(grad), _stream(stream)))
+
+
+def rt_plan_count(precision: int) -> int:
+    return int(load().rt_plan_count(int(precision)))
+
+
+def rt_plan_describe(precision: int, plan_id: int) -> dict:
+    info = rt_plan_info()
+    _check(load().rt_plan_describe(int(precision), int(plan_id), C.addressof(info)))
+    return {k: getattr(info, k) for k, _ in rt_plan_info._fields_}
+
+
+def rt_force_plan(precision: int, plan_id: int):
+    _check(load().rt_force_plan(int(precision), int(plan_id)))
+
+
+def rt_autotune(cosmo, z_source: float, table: FieldTable, precision: int, step_begin: int, n_probe_steps: int,
+                n_bundles: int, rays, stream=None) -> int:
+    best = C.c_int32(-1)
+    _check(load().rt_autotune(C.byref(cosmo), float(z_source), table.ptr, table.n, int(precision), int(step_begin),
+                              int(n_probe_steps), int(n_bundles), _dptr(rays), C.addressof(best), _stream(stream)))
+    return best.value
+
+
+def rt_enable_timing(on: bool):
+    _check(load().rt_enable_timing(1 if on else 0))
+
+
+def rt_last_trace_info() -> dict:
+    info = rt_trace_info()
+    _check(load().rt_last_trace_info(C.addressof(info)))
+    return {k: getattr(info, k) for k, _ in rt_trace_info._fields_}
+
+
+def rt_last_error() -> str:
+    return load().rt_last_error().decode()
+
+
+def rt_release_caches():
+    load().rt_release_caches()

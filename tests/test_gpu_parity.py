@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Element-by-element comparisons on the same seeded inputs, at sizes the oracle
+finishes in seconds while spanning several particle tiles with ragged tails.
+Tolerances:
+  * FP64 GPU vs oracle: mu within 1e-7 relative (1/mu within 1e-7 when |mu| > 100),
+    exit positions within 1e-7 of the deflection plus 1e-12 Mpc, lookback
+    time and wave vector within 1e-12 relative.  (The stated contract is 1e-4;
+    observed differences are round-off amplified along the path.)
+  * FP32+Kahan GPU vs oracle: |dmu| / (|mu| max(1, |mu|)) <= 1e-4, i.e. 1e-4 relative
+    for |mu| <= 1 and 1e-4 in 1/mu (the Jacobian determinant) beyond, because
+    near critical curves mu = 1/det amplifies any field error by |mu|; plain
+    relative mu error <= 1e-4 for weakly lensed bundles (|mu - 1| < 0.5); exit
+    positions within 1e-3 of the deflection.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc
+from paper_1110_4894_amd import rt
+from paper_1110_4894_amd import workloads as wl
+from tests.oracle_run import oracle_run
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32K = rt.RT_FP64, rt.RT_FP32_KAHAN
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()
+    yield
+    rt.rt_force_plan(FP64, -1)
+    rt.rt_force_plan(FP32K, -1)
+
+
+def _run(w, precision, **kw):
+    from paper_1110_4894_amd.runner import GpuRun
+    g = GpuRun(w)
+    return g.run(precision, **kw), g
+
+
+def mu_error(mu, ref):
+    """Relative mu error; for |mu| > 100, 100 |d(1/mu)| (equal to it at |mu| = 100)."""
+    mu, ref = np.asarray(mu), np.asarray(ref)
+    big = np.abs(ref) > 100
+    err = np.abs(mu - ref) / np.abs(ref)
+    err[big] = np.abs(1 / mu[big] - 1 / ref[big]) * 100.0
+    return err
+
+
+def _check_fp64(g, o, theta):
+    assert np.array_equal(g["flags"], o["flags"])
+    assert np.max(mu_error(g["mu"], o["mu"])) < 1e-7
+    gr, orr = g["rays"], o["rays"]
+    th = np.repeat(theta, 9, axis=1)
+    defl = np.hypot(orr[1] - th[0] * o["chi_s"], orr[2] - th[1] * o["chi_s"])
+    d = np.hypot(gr[1] - orr[1], gr[2] - orr[2])
+    assert np.all(d <= 1e-7 * defl + 1e-12)
+    # z = the last node, i.e. each side's own chi_s (they differ in the last bits)
+    assert np.all(np.abs(gr[3] - orr[3]) <= 1e-14 * orr[3])
+    for c in (0, 4, 5, 6, 7):
+        scale = np.max(np.abs(orr[c])) if c in (5, 6) else np.abs(orr[c])
+        assert np.all(np.abs(gr[c] - orr[c]) <= 1e-12 * scale + 1e-300), c
+    assert np.allclose(g["jac"], o["jac"], rtol=0, atol=1e-7 * max(1.0, np.abs(o["jac"]).max()))
+
+
+def mixed_error(mu, ref):
+    """Conditioning-scaled mu error |dmu| / (|mu| max(1, |mu|)), i.e. the error in 1/mu
+    (the Jacobian determinant) for |mu| > 1 and the relative error otherwise."""
+    mu, ref = np.asarray(mu), np.asarray(ref)
+    return np.abs(mu - ref) / (np.abs(ref) * np.maximum(1.0, np.abs(ref)))
+
+
+def _check_fp32(g, o, theta, tol_mu=1e-4):
+    assert np.array_equal(g["flags"], o["flags"])
+    assert np.max(mixed_error(g["mu"], o["mu"])) < tol_mu
+    weak = np.abs(o["mu"] - 1) < 0.5
+    assert np.max(mu_error(g["mu"][weak], o["mu"][weak])) < tol_mu
+    gr, orr = g["rays"], o["rays"]
+    th = np.repeat(theta, 9, axis=1)
+    defl = np.hypot(orr[1] - th[0] * o["chi_s"], orr[2] - th[1] * o["chi_s"])
+    d = np.hypot(gr[1] - orr[1], gr[2] - orr[2])
+    assert np.all(d <= 1e-3 * defl + 1e-12)
+
+
+# --------------------------------------------------------------------------- field kernel
+def _set_for(n, eps, seed=3, background=False):
+    rng = np.random.default_rng(seed)
+    xyz = rng.normal(size=(n, 3)) * 0.5 + np.array([0.1, -0.2, 1000.0])
+    m = rng.uniform(1e9, 1e11, n)
+    lo, hi = (-3.0, -3.0, 997.0), (3.0, 3.0, 1003.0)
+    return xyz, m, eps, background, lo, hi
+
+
+@pytest.mark.parametrize("n", [1, 63, 256, 1000, 4099])
+@pytest.mark.parametrize("background", [False, True])
+def test_field_eval_parity(n, background):
+    xyz, m, eps, bg, lo, hi = _set_for(n, 0.01, background=background)
+    c = orc.cosmo()
+    ps = orc.ParticleSet(xyz=xyz, m=m, softening=eps, background=bg, lo=lo, hi=hi)
+    rng = np.random.default_rng(n)
+    pts = rng.normal(size=(3, 300)) * 0.3 + np.array([[0.0], [0.0], [1000.0]])
+    ref_phi = np.zeros(300)
+    ref_g = np.zeros((3, 300))
+    for i in range(300):
+        ref_phi[i], ref_g[:, i] = orc.field_at(c, ps, pts[:, i])
+    dev = torch.device("cuda")
+    xyzm = torch.from_numpy(np.ascontiguousarray(np.concatenate([xyz.T, m[None]], 0))).to(dev)
+    pset = rt.make_particle_set(xyzm, eps, bg, lo, hi)
+    P = torch.from_numpy(np.ascontiguousarray(pts)).to(dev)
+    for prec, tol in ((FP64, 1e-12), (FP32K, 3e-5)):
+        phi = torch.empty(300, dtype=torch.float64, device=dev)
+        grad = torch.empty((3, 300), dtype=torch.float64, device=dev)
+        rt.rt_field_eval(rt.cosmology(), pset, prec, 300, P, phi, grad)
+        torch.cuda.synchronize()
+        gphi, gg = phi.cpu().numpy(), grad.cpu().numpy()
+        assert np.all(np.abs(gphi - ref_phi) <= tol * np.abs(ref_phi)), prec
+        gs = np.linalg.norm(ref_g, axis=0)
+        assert np.all(np.abs(gg - ref_g) <= tol * gs + 1e-30), prec
+
+
+# --------------------------------------------------------------------------- bundles
+def test_build_bundles_parity():
+    w = wl.schwarzschild(n_radii=3, n_azimuth=5)
+    # a mass near the observer so that phi_obs matters
+    w.fields[0].sets[0].xyz = np.array([[0.002, 0.001, 0.05]])
+    from tests.oracle_run import oracle_fields
+    c, chi_s, fields, theta = oracle_fields(w)
+    ref = orc.build_bundles(c, fields, theta, w.bundle_radius)
+    from paper_1110_4894_amd.runner import GpuRun
+    g = GpuRun(w)
+    g.build_bundles()
+    torch.cuda.synchronize()
+    got = g.rays.cpu().numpy()
+    assert np.allclose(got, ref, rtol=1e-15, atol=0)
+
+
+# --------------------------------------------------------------------------- trace
+def _schw(nb=12):
+    w = wl.schwarzschild(n_radii=4, n_azimuth=3)
+    return w
+
+
+def test_schwarzschild_fp64_parity():
+    w = _schw()
+    o = oracle_run(w)
+    g, _ = _run(w, FP64)
+    _check_fp64(g, o, o["theta"])
+
+
+def _small_nfw(n_part=3001, n_side=4, n_fine=150, radius=1e-3):
+    w = wl.nfw(n_side=n_side, n_part=n_part, n_fine=n_fine, radius_arcsec=radius)
+    return w
+
+
+def test_nfw_fp64_and_fp32_parity():
+    w = _small_nfw()
+    o = oracle_run(w)
+    g64, _ = _run(w, FP64)
+    _check_fp64(g64, o, o["theta"])
+    g32, _ = _run(w, FP32K)
+    _check_fp32(g32, o, o["theta"])
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32K])
+def test_every_plan_passes_parity(prec):
+    w = _small_nfw(n_part=2049, n_side=5, n_fine=60)
+    o = oracle_run(w)
+    try:
+        for pid in range(rt.rt_plan_count(prec)):
+            rt.rt_force_plan(prec, pid)
+            g, _ = _run(w, prec)
+            (_check_fp64 if prec == FP64 else _check_fp32)(g, o, o["theta"])
+    finally:
+        rt.rt_force_plan(prec, -1)
+
+
+def _small_box():
+    return wl.box(n_part_log2=12, n_side=3, n_steps=150)
+
+
+def test_box_parity_with_background():
+    w = _small_box()
+    o = oracle_run(w)
+    g64, _ = _run(w, FP64)
+    _check_fp64(g64, o, o["theta"])
+    g32, _ = _run(w, FP32K)
+    _check_fp32(g32, o, o["theta"])
+
+
+def test_empty_field_unit_magnification():
+    w = wl.empty(n_bundles=30)
+    g, _ = _run(w, FP64)
+    assert np.max(np.abs(g["mu"] - 1)) < 1e-8
+    g, _ = _run(w, FP32K)
+    assert np.max(np.abs(g["mu"] - 1)) < 1e-8
+
+
+def test_several_uneven_fields_in_one_launch():
+    a = wl.schwarzschild(n_radii=2, n_azimuth=3)
+    b = _small_nfw(n_part=777, n_side=3, n_fine=80)
+    e = wl.empty(n_bundles=4)
+    w = wl.Workload("mix", a.cosmology, a.z_source, a.bundle_radius, a.fields + b.fields + e.fields)
+    o = oracle_run(w)
+    g, _ = _run(w, FP64)
+    _check_fp64(g, o, o["theta"])
+    g, _ = _run(w, FP32K)
+    _check_fp32(g, o, o["theta"])
+
+
+def test_resume_is_bitwise_identical_and_deterministic():
+    w = _small_nfw(n_part=1500, n_side=3, n_fine=100)
+    from paper_1110_4894_amd.runner import GpuRun
+    for prec in (FP64, FP32K):
+        g = GpuRun(w)
+        full = g.run(prec)["rays"]
+        again = g.run(prec)["rays"]
+        assert np.array_equal(full, again)
+        g.build_bundles()
+        g.trace(prec, 0, 37)
+        g.trace(prec, 37, 2 ** 31 - 1)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.rays.cpu().numpy(), full)
+
+
+def test_graph_replay_matches_eager_each_time():
+    """The captured graph is replayed with host work and synchronisation in between;
+    every replay reproduces the first result."""
+    w = _small_nfw(n_part=900, n_side=3, n_fine=60)
+    from paper_1110_4894_amd.runner import GpuRun
+    g = GpuRun(w)
+    first = g.run(FP32K)
+    for _ in range(3):
+        g.build_bundles()
+        g.trace(FP32K)
+        info = rt.rt_last_trace_info()
+        assert info["graph_reused"] == 1
+        g.magnification()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.mu.cpu().numpy(), first["mu"])
+
+
+def test_magnification_and_histogram_parity():
+    # magnification of oracle-traced rays
+    w = _small_nfw(n_part=1000, n_side=4, n_fine=80)
+    o = oracle_run(w)
+    dev = torch.device("cuda")
+    rays = torch.from_numpy(o["rays"]).to(dev)
+    nb = o["mu"].shape[0]
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    jac = torch.empty((4, nb), dtype=torch.float64, device=dev)
+    c = rt.cosmology()
+    rt.rt_magnification(c, w.z_source, nb, w.bundle_radius, rays, mu, jac)
+    torch.cuda.synchronize()
+    assert np.allclose(mu.cpu().numpy(), o["mu"], rtol=1e-12, atol=0)
+    assert np.allclose(jac.cpu().numpy(), o["jac"], rtol=0, atol=1e-12)
+    # histogram of a wide synthetic mu sample, including excluded and out-of-range values
+    rng = np.random.default_rng(4)
+    mus = np.concatenate([np.exp(rng.normal(0, 0.08, 20011)), [-1.0, 0.0, 0.3, 7.0]])
+    ref_pdf, ref_mom = orc.mu_histogram(mus, 200, -0.1, 0.3)
+    m = torch.from_numpy(mus).to(dev)
+    pdf = torch.empty(200, dtype=torch.float64, device=dev)
+    mom = torch.empty(6, dtype=torch.float64, device=dev)
+    rt.rt_mu_histogram(len(mus), m, 200, -0.1, 0.3, pdf, mom)
+    torch.cuda.synchronize()
+    assert np.allclose(pdf.cpu().numpy(), ref_pdf, rtol=1e-12, atol=1e-14)
+    assert np.allclose(mom.cpu().numpy(), ref_mom, rtol=1e-12, atol=0)
