@@ -12,9 +12,10 @@ with the persistent kernel), magnification and the muPDF.  Eight steps cover
 the whole grid; steps cycle through the bands.  Inputs (particles, bundle
 directions) are resident in HBM before the timed region.
 
-Untimed: the same bands' every 16th bundle is also traced in FP64 to give
-the mixed-vs-FP64 mu error and the FP64 throughput; the CPU oracle is timed
-on two bundles of the batch (full schedule, all particles).
+Untimed: every second bundle of the first timed band is also traced in FP64
+(4096 bundles, enough to fill the GPU) to give the mixed-vs-FP64 mu error and
+the FP64 throughput; the CPU oracle is timed on two bundles of the batch (full
+schedule, all particles).
 
 Prints one JSON line.
 """
@@ -47,11 +48,14 @@ def parse():
     p.add_argument("--bands", type=int, default=8, help="bundle-grid bands (one band = one step)")
     p.add_argument("--n-side", type=int, default=256)
     p.add_argument("--n-part", type=int, default=100_000)
-    p.add_argument("--fp64-stride", type=int, default=16, help="every k-th bundle of a band traced in FP64")
+    p.add_argument("--fp64-stride", type=int, default=2, help="every k-th bundle of one band traced in FP64")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--cpu-bundles", type=int, default=2)
+    p.add_argument("--plan", type=int, default=-1, help="force a trace plan (skips the autotuner)")
+    p.add_argument("--copy-calibration", type=int, default=0,
+                   help="only copy a buffer of this many MiB (HBM counter calibration) and exit")
     return p.parse_args()
 
 
@@ -80,6 +84,14 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n}), flush=True)
+        return
     rt.load()
 
     t_setup = time.time()
@@ -100,7 +112,10 @@ def main():
           % (band, n_steps_path, a.n_part, inter_per_step, time.time() - t_setup), file=sys.stderr, flush=True)
 
     tuned = None
-    if not a.no_autotune:
+    if a.plan >= 0:
+        rt.rt_force_plan(rt.RT_FP32_KAHAN, a.plan)
+        tuned = a.plan
+    elif not a.no_autotune:
         g.build_bundles()
         mid = n_steps_path // 2
         tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, rt.RT_FP32_KAHAN, mid, 6, g.n_bundles, g.rays)
@@ -164,7 +179,7 @@ def main():
     if not a.no_fp64:
         errs = []
         f64_ms, f64_inter = [], 0.0
-        for bi, m32 in sorted(mu32.items()):
+        for bi, m32 in sorted(mu32.items())[:1]:
             sub = np.ascontiguousarray(bands[bi][:, ::a.fp64_stride])
             ws = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
                                     [workloads.FieldSpec(f.name, f.sets, sub, f.schedule, f.replica_box, {})])

@@ -176,6 +176,10 @@ rt_status rt_plan_describe(rt_precision precision, int32_t id, rt_plan_info* inf
 /* Force plan `id` for every later rt_trace of this precision (-1 returns to automatic choice). */
 rt_status rt_force_plan(rt_precision precision, int32_t id);
 
+/* Cap the number of workgroups of the persistent trace launch (0 = as many as fit on the device).
+ * Results do not depend on it: every workgroup drains the same work queue. */
+rt_status rt_set_grid_limit(int32_t max_blocks);
+
 /* Time every plan on steps [step_begin, step_begin + n_probe_steps) of the given fields, on a
  * library-owned copy of `rays` (the caller's rays are not modified), and keep the fastest for
  * later rt_trace calls of the same precision and workload class.  best_id: host, or NULL. */

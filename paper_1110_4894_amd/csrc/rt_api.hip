@@ -223,6 +223,7 @@ struct State {
   std::mutex mu;
   std::vector<std::unique_ptr<TraceEntry>> cache;   // most recent last
   int forced[2] = {-1, -1};
+  int grid_limit = 0;
   std::map<std::tuple<int, int, int, int>, int> tuned;   // (device, fp64, log2 rays, log2 mean np) -> plan
   hipStream_t capture_stream[64] = {};
   bool timing = false;
@@ -256,6 +257,7 @@ std::vector<uint8_t> make_key(int dev, const rt_cosmology& c, const rt_field* fi
   put(k, nb);
   put(k, rays);
   put(k, flags);
+  put(k, g.grid_limit);
   put(k, n_fields);
   for (int f = 0; f < n_fields; ++f) {
     const rt_field& F = fields[f];
@@ -446,6 +448,7 @@ rt_status build_entry(TraceEntry* e, const DeviceInfo& di, const rt_cosmology& c
   RT_HIP(plan_occupancy(fp64, plan, &per_cu));
   if (per_cu < 1) return fail(RT_ERR_DEVICE, "trace plan %d does not fit on a compute unit", plan);
   e->grid = std::max(1, std::min(e->n_items, per_cu * di.n_cu));
+  if (g.grid_limit > 0) e->grid = std::min(e->grid, g.grid_limit);
   e->interactions = describe(fields, n_fields, sb, se).interactions;
   return RT_OK;
 }
@@ -758,6 +761,13 @@ rt_status rt_force_plan(rt_precision precision, int32_t id) {
   if (id < -1 || id >= plan_count(precision == RT_FP64)) return fail(RT_ERR_INVALID_ARG, "plan id %d out of range", id);
   std::lock_guard<std::mutex> lk(g.mu);
   g.forced[precision == RT_FP64] = id;
+  return RT_OK;
+}
+
+rt_status rt_set_grid_limit(int32_t max_blocks) {
+  if (max_blocks < 0) return fail(RT_ERR_INVALID_ARG, "max_blocks < 0");
+  std::lock_guard<std::mutex> lk(g.mu);
+  g.grid_limit = max_blocks;
   return RT_OK;
 }
 

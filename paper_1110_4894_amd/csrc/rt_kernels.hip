@@ -30,7 +30,7 @@ namespace rt {
 
 namespace {
 
-constexpr int kKahanChunk = 32;     // particles summed plainly before a Kahan update
+constexpr int kKahanChunk = 64;     // particles summed plainly before a Kahan update
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -58,7 +58,7 @@ class rt_trace_info(C.Structure):
 
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
            "rt_magnification", "rt_mu_histogram", "rt_field_eval", "rt_plan_count", "rt_plan_describe",
-           "rt_force_plan", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
+           "rt_force_plan", "rt_set_grid_limit", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
            "rt_release_caches"]
 
 _lib = None
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "rt_plan_count": (i32, [st]),
         "rt_plan_describe": (st, [st, i32, p]),
         "rt_force_plan": (st, [st, i32]),
+        "rt_set_grid_limit": (st, [i32]),
         "rt_autotune": (st, [p, d, p, i32, st, i32, i32, i64, p, p, p]),
         "rt_enable_timing": (st, [i32]),
         "rt_last_trace_info": (st, [p]),
@@ -232,6 +233,10 @@ def rt_plan_describe(precision: int, plan_id: int) -> dict:
 
 def rt_force_plan(precision: int, plan_id: int):
     _check(load().rt_force_plan(int(precision), int(plan_id)))
+
+
+def rt_set_grid_limit(max_blocks: int):
+    _check(load().rt_set_grid_limit(int(max_blocks)))
 
 
 def rt_autotune(cosmo, z_source: float, table: FieldTable, precision: int, step_begin: int, n_probe_steps: int,

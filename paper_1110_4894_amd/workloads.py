@@ -14,7 +14,10 @@ Workloads (cosmology Omega_m = 0.3, Omega_Lambda = 0.7, h = 0.7 throughout):
     (M200 = 1e14 Msun, c = 5) at z_l = 0.25; 256 x 256 bundles over +-3 r_s.
   * ``box``: a Zel'dovich-displaced periodic box (100 Mpc/h, P(k) ~ k^-1.5,
     sigma_8 = 0.8), replicated along the line of sight with random periodic
-    shifts and 90-degree rotations (Sec. 5.2), 2^18 or 2^20 particles.
+    shifts and 90-degree rotations (Sec. 5.2), 2^18 or 2^20 particles;
+    bundle radius 0.1 arcsec, one of the radii of Sec. 4.2.
+  * ``batched``: 64 uneven fields (point-mass groups, NFW haloes, box
+    sub-volumes), bundle radius 0.1 arcsec.
 
 Seeds: master seed 1110; each object draws from its own child of
 ``numpy.random.SeedSequence(seed)``.
@@ -266,7 +269,7 @@ def box_replicas(pos: np.ndarray, box: float, n_rep: int, rng: np.random.Generat
 
 
 def box(n_part_log2: int = 18, n_side: int = 128, z_s: float = 0.5, fov_deg: float = 1.0,
-        radius_arcsec: float = 1e-3, n_steps: int = 2000, box_mpc_h: float = 100.0,
+        radius_arcsec: float = 0.1, n_steps: int = 2000, box_mpc_h: float = 100.0,
         soft_kpc_h: float = 50.0, seed: int = MASTER_SEED, n_replicas: Optional[int] = None) -> Workload:
     cos = Cosmology()
     L = box_mpc_h / cos.h
@@ -322,3 +325,90 @@ def subsample(w: Workload, stride: int, offset: int = 0, max_bundles: Optional[i
                 meta[k] = v[offset::stride][: th.shape[1]]
         fields.append(FieldSpec(f.name, f.sets, np.ascontiguousarray(th), f.schedule, f.replica_box, meta))
     return Workload(w.name, w.cosmology, w.z_source, w.bundle_radius, fields, dict(w.meta))
+
+
+# ----------------------------------------------------------------------------- batched uneven fields
+def batched(n_sides=(64, 128, 256), side_override: Optional[int] = None, z_s: float = 0.5,
+            radius_arcsec: float = 0.1, n_fine: int = 500, q: float = 1.1, seed: int = MASTER_SEED,
+            n_point: int = 16, n_nfw: int = 32, n_box: int = 16, nfw_np_range=(10_000, 1_000_000),
+            box_sub_mpc_h: float = 25.0) -> Workload:
+    """64 independent lens fields of very uneven cost, in this order:
+    16 groups of 1-8 point masses (log-uniform 1e11-1e13 Msun, z_l ~ U[0.1, 0.4]);
+    32 NFW haloes (N_p log-uniform in [1e4, 1e6], M200 log-uniform in [1e13, 1e15] Msun,
+    c ~ U[4, 8], z_l ~ U[0.1, 0.4], softening 2 kpc physical);
+    16 sub-volumes (25 Mpc/h cubes) cut from the 2^20-particle Zel'dovich box and
+    placed at a seeded distance, with their uniform-cuboid background.
+    Each field gets a seeded 64^2, 128^2 or 256^2 bundle grid (``side_override``
+    replaces the side, to run reduced versions) and 500 fine steps across its mass."""
+    cos = Cosmology()
+    chi_s = cos.comoving(z_s)
+    rng_master = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    rngs = [np.random.default_rng(s) for s in np.random.SeedSequence(seed + 5).spawn(n_point + n_nfw + n_box + 1)]
+    fields: List[FieldSpec] = []
+
+    def grid(half: float, side: int):
+        pitch = 2 * half / side
+        g = -half + pitch * (np.arange(side) + 0.5)
+        ty, tx = np.meshgrid(g, g, indexing="ij")
+        return np.stack([tx.ravel(), ty.ravel()])
+
+    def pick_side(r):
+        s = int(r.choice(np.asarray(n_sides)))
+        return side_override if side_override is not None else s
+
+    for i in range(n_point):
+        r = rngs[i]
+        k = int(r.integers(1, 9))
+        masses = 10 ** r.uniform(11, 13, k)
+        z_l = r.uniform(0.1, 0.4)
+        chi_l = cos.comoving(z_l)
+        th_e = einstein_angle(cos, masses.sum(), z_l, z_s)
+        pos = np.zeros((k, 3))
+        pos[:, :2] = r.normal(size=(k, 2)) * th_e * chi_l
+        pos[:, 2] = chi_l + r.uniform(-0.5, 0.5, k)
+        side = pick_side(r)
+        half = 3 * th_e
+        fields.append(FieldSpec("points-%d" % i, [ParticleSetSpec(pos, masses, 0.0)], grid(half, side),
+                                {"z_lo": chi_l - 1.0, "z_hi": chi_l + 1.0, "n_fine": n_fine, "q": q},
+                                meta={"kind": "points", "n": k}))
+    lo_np, hi_np = nfw_np_range
+    for i in range(n_nfw):
+        r = rngs[n_point + i]
+        n_part = int(round(10 ** r.uniform(np.log10(lo_np), np.log10(hi_np))))
+        m200 = 10 ** r.uniform(13, 15)
+        conc = r.uniform(4, 8)
+        z_l = r.uniform(0.1, 0.4)
+        chi_l = cos.comoving(z_l)
+        xyz, m, meta = nfw_halo_spec(cos, m200, conc, z_l, n_part, r, (0.0, 0.0, chi_l))
+        d_d = chi_l / (1 + z_l)
+        r200c = meta["r200_phys"] * (1 + z_l)
+        side = pick_side(r)
+        half = 3 * meta["rs_phys"] / d_d
+        fields.append(FieldSpec("nfw-%d" % i, [ParticleSetSpec(xyz, m, 2e-3 * (1 + z_l))], grid(half, side),
+                                {"z_lo": chi_l - r200c, "z_hi": chi_l + r200c, "n_fine": n_fine, "q": q},
+                                meta=dict(meta, kind="nfw", n=n_part)))
+    # the parent box of the sub-volumes: 2^20 particles of the 128^3 Zel'dovich field
+    L = 100.0 / cos.h
+    r_box = rngs[-1]
+    pos = zeldovich_positions(128, L, r_box, h=cos.h)
+    keep = r_box.choice(pos.shape[0], size=2 ** 20, replace=False)
+    pos = pos[np.sort(keep)]
+    m_p = cos.omega_m * cos.rho_crit(0.0) * L ** 3 / pos.shape[0]
+    sub = box_sub_mpc_h / cos.h
+    n_cells = int(round(L / sub))
+    for i in range(n_box):
+        r = rngs[n_point + n_nfw + i]
+        cx, cy, cz = (int(v) for v in r.integers(0, n_cells, 3))
+        lo = np.array([cx, cy, cz]) * sub
+        sel = np.all((pos >= lo) & (pos < lo + sub), axis=1)
+        p = pos[sel] - lo - 0.5 * sub                 # centred cube
+        z0 = r.uniform(0.2, 0.8) * chi_s              # near face of the slab
+        p[:, 2] += z0 + 0.5 * sub
+        side = pick_side(r)
+        half = 0.4 * sub / (z0 + sub)                 # 0.8 x the cube's angular width at its far face
+        fields.append(FieldSpec("box-%d" % i, [ParticleSetSpec(p, np.full(len(p), m_p), 0.05 / cos.h, True,
+                                                               (-0.5 * sub, -0.5 * sub, z0),
+                                                               (0.5 * sub, 0.5 * sub, z0 + sub))],
+                                grid(half, side), {"z_lo": z0, "z_hi": z0 + sub, "n_fine": n_fine, "q": q},
+                                meta={"kind": "box", "n": int(len(p))}))
+    return Workload("batched", cos, z_s, radius_arcsec * ARCSEC, fields, meta={"chi_s": chi_s})

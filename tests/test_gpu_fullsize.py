@@ -1,0 +1,148 @@
+"""Parity at the workloads' full sizes (full particle sets and full RK4
+schedules), on sampled bundles that the CPU oracle traces one by one.
+
+* point lens (32 x 32 bundles, 1225 steps, FP64): every bundle against the oracle
+  and against the Schwarzschild magnification;
+* NFW halo (1e5 particles, 2236 steps): one band of 8192 bundles traced exactly as
+  bench.py times it (FP32 pair terms, autotuned plan), sampled bundles against
+  the oracle, and FP64 on the same bundles;
+* Zel'dovich boxes (2^18 and 2^20 particles in 14 replicas, 2000 steps): bands of
+  bundles in FP32, sampled bundles against the oracle;
+* 64 uneven fields in one launch (bundle grids reduced to 8 x 8 per field):
+  FP32 vs FP64 over every bundle and the oracle on one bundle of several fields.
+Tolerances as in test_gpu_parity.py.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc
+from paper_1110_4894_amd import rt
+from paper_1110_4894_amd import workloads as wl
+from tests.oracle_run import oracle_run
+from tests.test_gpu_parity import _check_fp32, _check_fp64, mixed_error, mu_error
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32K = rt.RT_FP64, rt.RT_FP32_KAHAN
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()
+
+
+def _with_theta(w, theta_per_field):
+    fields = [wl.FieldSpec(f.name, f.sets, np.ascontiguousarray(th), f.schedule, f.replica_box, dict(f.meta))
+              for f, th in zip(w.fields, theta_per_field)]
+    return wl.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius, fields, dict(w.meta))
+
+
+def _gpu_run(w, prec, tune=False):
+    from paper_1110_4894_amd.runner import GpuRun
+    g = GpuRun(w)
+    if tune:
+        g.build_bundles()
+        rt.rt_autotune(g.cosmo, w.z_source, g.table, prec, g.max_steps // 2, 6, g.n_bundles, g.rays)
+    return g.run(prec)
+
+
+def _pick(o_len, idx):
+    return np.asarray(idx)
+
+
+def test_point_lens_full():
+    w = wl.schwarzschild()
+    o = oracle_run(w)
+    g = _gpu_run(w, FP64)
+    _check_fp64(g, o, o["theta"])
+    x = w.fields[0].meta["x"]
+    want = 1 / (1 - x ** -4)
+    far = x >= 2
+    assert np.max(np.abs(g["mu"][far] / want[far] - 1)) < 1e-5
+    near = x <= 1.1
+    assert np.all(np.abs(1 / g["mu"][near] - (1 - x[near] ** -4)) < 3e-4 * np.maximum(1, np.abs(1 - x[near] ** -4)))
+
+
+def test_nfw_full_band_as_benchmarked():
+    w = wl.nfw()
+    f = w.fields[0]
+    band = f.n_bundles // 8
+    b = 4                                  # a band through the halo centre
+    th = f.theta[:, b * band:(b + 1) * band]
+    wb = _with_theta(w, [th])
+    g = _gpu_run(wb, FP32K, tune=True)
+    row = 16 * 256                         # middle row of the band
+    sample = np.array([row + 128, row + 135, row + 60])
+    ws = _with_theta(w, [th[:, sample]])
+    o = oracle_run(ws)
+    sub = {"mu": g["mu"][sample], "flags": g["flags"][(9 * sample[:, None] + np.arange(9)).ravel()],
+           "rays": g["rays"][:, (9 * sample[:, None] + np.arange(9)).ravel()], "chi_s": g["chi_s"]}
+    _check_fp32(sub, o, o["theta"])
+    g64 = _gpu_run(ws, FP64)
+    _check_fp64(g64, o, o["theta"])
+    assert np.max(np.abs(o["mu"] - 1)) > 0.05        # the sample is lensed
+
+
+@pytest.mark.parametrize("log2n,n_side,rows", [(18, 128, 8), (20, 512, 1)])
+def test_box_full_sampled(log2n, n_side, rows):
+    w = wl.box(n_part_log2=log2n, n_side=n_side)
+    f = w.fields[0]
+    mid = n_side // 2
+    th = f.theta[:, (mid - rows // 2) * n_side: (mid - rows // 2 + rows) * n_side]
+    if log2n == 20:
+        th = th[:, :126]                   # 2 wavefront groups of bundles at full particle count
+    wb = _with_theta(w, [th])
+    g = _gpu_run(wb, FP32K)
+    sample = np.array([5]) if log2n == 20 else np.array([3, th.shape[1] // 2 + 7])
+    ws = _with_theta(w, [th[:, sample]])
+    o = oracle_run(ws)
+    sub = {"mu": g["mu"][sample], "flags": g["flags"][(9 * sample[:, None] + np.arange(9)).ravel()],
+           "rays": g["rays"][:, (9 * sample[:, None] + np.arange(9)).ravel()], "chi_s": g["chi_s"]}
+    _check_fp32(sub, o, o["theta"])
+    # the same bundles in FP64 on the GPU
+    g64 = _gpu_run(ws, FP64)
+    _check_fp64(g64, o, o["theta"])
+    # mean-density subtraction keeps the box weakly lensing
+    assert np.all(np.abs(g["mu"] - 1) < 0.5)
+
+
+def test_uneven_fields_one_launch():
+    w = wl.batched(side_override=8)
+    g32 = _gpu_run(w, FP32K)
+    info = rt.rt_last_trace_info()
+    assert info["n_items"] >= 64
+    g64 = _gpu_run(w, FP64)
+    assert np.array_equal(g32["flags"], g64["flags"])
+    assert np.max(mixed_error(g32["mu"], g64["mu"])) < 1e-4
+    # oracle on one bundle of a few fields of each kind (the cheaper ones)
+    order = {"points": [], "nfw": [], "box": []}
+    for i, f in enumerate(w.fields):
+        order[f.meta["kind"]].append((sum(len(s.m) for s in f.sets), i))
+    chosen = [i for k in order for _, i in sorted(order[k])[:2]]
+    thetas = []
+    keep = []
+    off = 0
+    for i, f in enumerate(w.fields):
+        if i in chosen:
+            thetas.append(f.theta[:, 27:28])
+            keep.append(off + 27)
+        off += f.n_bundles
+    ws = wl.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
+                     [wl.FieldSpec(w.fields[i].name, w.fields[i].sets, np.ascontiguousarray(t),
+                                   w.fields[i].schedule, w.fields[i].replica_box, {})
+                      for i, t in zip(chosen, thetas)])
+    o = oracle_run(ws)
+    keep = np.array(keep)
+    rays_idx = (9 * keep[:, None] + np.arange(9)).ravel()
+    sub64 = {"mu": g64["mu"][keep], "flags": g64["flags"][rays_idx], "rays": g64["rays"][:, rays_idx],
+             "jac": g64["jac"][:, keep], "chi_s": g64["chi_s"]}
+    _check_fp64(sub64, o, o["theta"])
+    sub32 = {"mu": g32["mu"][keep], "flags": g32["flags"][rays_idx], "rays": g32["rays"][:, rays_idx],
+             "chi_s": g32["chi_s"]}
+    _check_fp32(sub32, o, o["theta"])

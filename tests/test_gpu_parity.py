@@ -109,8 +109,15 @@ def test_field_eval_parity(n, background):
     pts = rng.normal(size=(3, 300)) * 0.3 + np.array([[0.0], [0.0], [1000.0]])
     ref_phi = np.zeros(300)
     ref_g = np.zeros((3, 300))
+    scale_phi = np.zeros(300)
+    scale_g = np.zeros(300)
+    bare = orc.ParticleSet(xyz=xyz, m=m, softening=eps)
     for i in range(300):
         ref_phi[i], ref_g[:, i] = orc.field_at(c, ps, pts[:, i])
+        p0, g0 = orc.field_at(c, bare, pts[:, i])
+        # FP32 errors scale with the particle sum, which the cuboid term may cancel
+        scale_phi[i] = max(abs(p0), abs(ref_phi[i]))
+        scale_g[i] = max(np.linalg.norm(g0), np.linalg.norm(ref_g[:, i]))
     dev = torch.device("cuda")
     xyzm = torch.from_numpy(np.ascontiguousarray(np.concatenate([xyz.T, m[None]], 0))).to(dev)
     pset = rt.make_particle_set(xyzm, eps, bg, lo, hi)
@@ -121,9 +128,8 @@ def test_field_eval_parity(n, background):
         rt.rt_field_eval(rt.cosmology(), pset, prec, 300, P, phi, grad)
         torch.cuda.synchronize()
         gphi, gg = phi.cpu().numpy(), grad.cpu().numpy()
-        assert np.all(np.abs(gphi - ref_phi) <= tol * np.abs(ref_phi)), prec
-        gs = np.linalg.norm(ref_g, axis=0)
-        assert np.all(np.abs(gg - ref_g) <= tol * gs + 1e-30), prec
+        assert np.all(np.abs(gphi - ref_phi) <= tol * scale_phi), prec
+        assert np.all(np.abs(gg - ref_g) <= tol * scale_g + 1e-30), prec
 
 
 # --------------------------------------------------------------------------- bundles
@@ -272,3 +278,42 @@ def test_magnification_and_histogram_parity():
     torch.cuda.synchronize()
     assert np.allclose(pdf.cpu().numpy(), ref_pdf, rtol=1e-12, atol=1e-14)
     assert np.allclose(mom.cpu().numpy(), ref_mom, rtol=1e-12, atol=0)
+
+
+def test_result_independent_of_grid_size():
+    """The persistent launch drains one work queue: any number of workgroups gives
+    bitwise identical rays."""
+    w = _small_nfw(n_part=1200, n_side=6, n_fine=40)
+    from paper_1110_4894_amd.runner import GpuRun
+    try:
+        for prec in (FP64, FP32K):
+            rt.rt_set_grid_limit(0)
+            ref = GpuRun(w).run(prec)["rays"]
+            for lim in (1, 3, 7):
+                rt.rt_set_grid_limit(lim)
+                got = GpuRun(w).run(prec)["rays"]
+                assert np.array_equal(got, ref), (prec, lim)
+    finally:
+        rt.rt_set_grid_limit(0)
+
+
+def test_flags_outside_the_weak_field():
+    """A 1e17 Msun point mass: rays at ~50 kpc leave the weak-field regime (flag 4),
+    rays aimed at the mass turn back or blow up (flags 1/2) and keep their last good
+    state; the same rays are flagged on both sides and nothing faults."""
+    w = wl.schwarzschild(n_radii=1, n_azimuth=1, mass=1e17)
+    f = w.fields[0]
+    chi_l = f.meta["chi_l"]
+    b = np.array([50e-3, 80e-3, 1e-4, 2e-5, 300e-3])           # impact parameters, Mpc
+    ang = np.arange(len(b)) * 1.1
+    f.theta = np.stack([b / chi_l * np.cos(ang), b / chi_l * np.sin(ang)])
+    o = oracle_run(w)
+    for prec in (FP64, FP32K):
+        g, _ = _run(w, prec)
+        hard_o = (o["flags"] & 3) != 0
+        hard_g = (g["flags"] & 3) != 0
+        assert np.array_equal(hard_o, hard_g)
+        soft = ~hard_o
+        assert np.array_equal(o["flags"][soft] & 4, g["flags"][soft] & 4)
+        assert np.all(np.isfinite(g["rays"]))
+    assert hard_o.any() and (o["flags"] & 4).any()
