@@ -6,10 +6,11 @@ z_s = 0.5) with 256 x 256 bundles (anchor + 8 rays, radius 1e-3 arcsec) over
 +-3 r_s and 2000 fine RK4 steps across the halo (2237 steps in all).
 
 One step = one pass of the whole path over one batch of the bundle grid: a
-band of 32 rows (8192 bundles, 73 728 rays): bundle construction, tracing
-with FP32 pair terms + Kahan sums and FP64 integration (one captured graph
-with the persistent kernel), magnification and the muPDF.  Eight steps cover
-the whole grid; steps cycle through the bands.  Inputs (particles, bundle
+band of 7168 consecutive bundles (64 512 rays) of the row-major grid, sized to
+two full rounds of the trace kernel's resident workgroups: bundle
+construction, tracing with FP32 pair terms + Kahan sums and FP64 integration
+(one captured graph with the persistent kernel), magnification and the muPDF.
+Steps walk through the grid band after band.  Inputs (particles, bundle
 directions) are resident in HBM before the timed region.
 
 Untimed: every second bundle of the first timed band is also traced in FP64
@@ -36,6 +37,11 @@ if ROOT not in sys.path:
 
 METRIC = "ray-particle interactions/s and bundles/s at μ err ≤1e-4 vs FP64 (mixed vs FP64)"
 PEAK_FP32 = 157.3      # TFLOP/s, MI355X FP32 vector (published)
+# HBM bytes per launch of the FP32 trace kernel on this workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and 1.0),
+# keyed by the sha256 prefix of the kernel source they were taken with.
+MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0,
+                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 PEAK_FP64 = 78.6       # TFLOP/s, MI355X FP64 vector (published)
 FLOP_PER_INTERACTION = 20.0
 
@@ -43,9 +49,11 @@ FLOP_PER_INTERACTION = 20.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--bands", type=int, default=8, help="bundle-grid bands (one band = one step)")
+    p.add_argument("--band", type=int, default=7168,
+                   help="bundles per step: 7168 bundles = 1024 groups of 7 bundles, i.e. two full rounds of the "
+                        "512 workgroups that the trace kernel keeps resident on 256 CUs")
     p.add_argument("--n-side", type=int, default=256)
     p.add_argument("--n-part", type=int, default=100_000)
     p.add_argument("--fp64-stride", type=int, default=2, help="every k-th bundle of one band traced in FP64")
@@ -57,6 +65,18 @@ def parse():
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="only copy a buffer of this many MiB (HBM counter calibration) and exit")
     return p.parse_args()
+
+
+def traffic_bytes(band):
+    """Measured HBM bytes per trace launch, or None when the kernel source has changed
+    since the counters were taken (or the batch differs from the profiled one)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1110_4894_amd", "csrc", "rt_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    m = MEASURED_TRAFFIC.get(sha)
+    if m is None or band != 7168:
+        return None
+    return m["read"] + m["write"]
 
 
 def mu_stats(mu, ref):
@@ -98,8 +118,11 @@ def main():
     w = workloads.nfw(n_side=a.n_side, n_part=a.n_part)
     f = w.fields[0]
     nb_all = f.n_bundles
-    band = nb_all // a.bands
-    bands = [np.ascontiguousarray(f.theta[:, i * band:(i + 1) * band]) for i in range(a.bands)]
+    band = a.band
+    n_bands = -(-nb_all // band)
+    # consecutive bands of the row-major bundle grid, wrapping around at its end
+    bands = [np.ascontiguousarray(f.theta[:, (np.arange(i * band, (i + 1) * band) % nb_all)])
+             for i in range(n_bands)]
     w_batch = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
                                  [workloads.FieldSpec(f.name, f.sets, bands[0], f.schedule, f.replica_box, {})])
     uploads = {}
@@ -123,7 +146,7 @@ def main():
               flush=True)
 
     def one_step(i):
-        g.set_theta(theta_dev[i % a.bands])
+        g.set_theta(theta_dev[i % n_bands])
         g.build_bundles()
         g.trace(rt.RT_FP32_KAHAN)
         g.magnification()
@@ -143,7 +166,7 @@ def main():
         one_step(a.warmup + i)
         info = rt.rt_last_trace_info()      # waits for this step's trace graph (events on its stream)
         kernel_ms.append(info["kernel_ms"])
-        mu32[(a.warmup + i) % a.bands] = g.mu.clone()
+        mu32[(a.warmup + i) % n_bands] = g.mu.clone()
         print("step %d: trace %.1f ms, plan %d, grid %d, graph reused %d" % (
             i, info["kernel_ms"], info["plan_id"], info["grid_blocks"], info["graph_reused"]), file=sys.stderr,
             flush=True)
@@ -163,14 +186,15 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "nfw-halo 1e5 particles (M200 1e14 Msun, c 5, z_l 0.25, z_s 0.5), 256x256 "
                                "bundles over +-3 r_s, r_b 1e-3 arcsec, 2000 fine RK4 steps (%d in all); "
-                               "one step = one band of %d bundles" % (n_steps_path, band),
+                               "one step = one band of %d consecutive bundles" % (n_steps_path, band),
                    "bundles_per_step": band, "rays_per_step": 9 * band, "rk4_steps": n_steps_path,
                    "particles": a.n_part, "precision": "fp32-kahan field, fp64 integration",
                    "parallelism": "single GPU", "plan": tuned},
         "bundles_per_s": bundles_per_s,
         "interactions_per_step": inter_per_step,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "frac": achieved / PEAK_FP32, "traffic": traffic_bytes(band),
+                     "traffic_unit": "HBM bytes per launch (read + write)",
                      "kernel": "trace_kernel (fp32)", "kernel_ms": k_ms,
                      "flop_per_interaction": FLOP_PER_INTERACTION},
     }

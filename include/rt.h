@@ -154,6 +154,14 @@ rt_status rt_magnification(const rt_cosmology* cosmo, double z_source, int64_t n
 rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
                           double* pdf, double* moments, hipStream_t stream);
 
+/* Source-weighted shear PDF (the shear distribution of Sec. 5.4, weighted like eq. weighthisto):
+ * |gamma| = hypot(gamma1, gamma2) from rt_magnification's Jacobian, weight 1/mu for mu > 0,
+ * n_bins bins uniform in |gamma| over [lo, hi); pdf_i = sum_{b in i} w_b / (sum_b w_b dgamma).
+ * mu: device [n]; jac: device [4][n]; pdf: device [n_bins]; moments: device [6] = sum w,
+ * <|gamma|>_w, sigma_w, n(mu <= 0), n below, n above the range. */
+rt_status rt_shear_histogram(int64_t n, const double* mu, const double* jac, int32_t n_bins, double lo, double hi,
+                             double* pdf, double* moments, hipStream_t stream);
+
 /* The field kernel alone (Sec. 3.3): phi and grad phi of one particle set at n points, with the
  * same arithmetic rt_trace uses for the given precision.  points: device [3][n];
  * phi: device [n]; grad: device [3][n]. */

@@ -74,6 +74,7 @@ def _load():
             "or_trace": (i32, [cp, p, i32, i32, i32, i64, p, p, i32]),
             "or_magnification": (i32, [d, i64, d, p, p, p]),
             "or_mu_histogram": (i32, [i64, p, i32, d, d, p, p]),
+            "or_shear_histogram": (i32, [i64, p, p, i32, d, d, p, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -273,4 +274,15 @@ def mu_histogram(mu, n_bins: int = 200, log_lo: float = -0.1, log_hi: float = 0.
     rc = _load().or_mu_histogram(len(mu), _ptr(mu), n_bins, log_lo, log_hi, _ptr(pdf), _ptr(mom))
     if rc != 0:
         raise ValueError("or_mu_histogram failed")
+    return pdf, mom
+
+
+def shear_histogram(mu, jac, n_bins: int = 100, lo: float = 0.0, hi: float = 0.1):
+    mu = _f64(mu)
+    jac = _f64(jac).reshape(4, -1)
+    pdf = np.zeros(n_bins)
+    mom = np.zeros(6)
+    rc = _load().or_shear_histogram(len(mu), _ptr(mu), _ptr(jac), n_bins, lo, hi, _ptr(pdf), _ptr(mom))
+    if rc != 0:
+        raise ValueError("or_shear_histogram failed")
     return pdf, mom

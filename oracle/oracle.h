@@ -70,5 +70,7 @@ int or_trace(const or_cosmo* c, const or_field* fields, int32_t n_fields, int32_
 int or_magnification(double chi_s, int64_t n_bundles, double radius, const double* rays, double* mu, double* jac);
 int or_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
                     double* pdf, double* moments);
+int or_shear_histogram(int64_t n, const double* mu, const double* jac, int32_t n_bins, double lo, double hi,
+                       double* pdf, double* moments);
 
 #endif

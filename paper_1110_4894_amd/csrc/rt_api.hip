@@ -702,7 +702,22 @@ rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double lo
   if (!(log_hi > log_lo)) return fail(RT_ERR_INVALID_ARG, "log_hi must exceed log_lo");
   void* work = nullptr;
   RT_HIP(hipMallocAsync(&work, sizeof(double) * (n_bins + 8), stream));
-  RT_HIP(launch_histogram(n, mu, n_bins, log_lo, log_hi, pdf, moments, static_cast<double*>(work), stream));
+  RT_HIP(launch_histogram(n, mu, nullptr, 0, n_bins, log_lo, log_hi, pdf, moments, static_cast<double*>(work), stream));
+  RT_HIP(hipFreeAsync(work, stream));
+  return RT_OK;
+}
+
+rt_status rt_shear_histogram(int64_t n, const double* mu, const double* jac, int32_t n_bins, double lo, double hi,
+                             double* pdf, double* moments, hipStream_t stream) {
+  if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");
+  if (n > 0 && (!mu || !jac)) return fail(RT_ERR_INVALID_ARG, "mu or jac is NULL");
+  if (!pdf || !moments) return fail(RT_ERR_INVALID_ARG, "pdf or moments is NULL");
+  if (n_bins < 1 || n_bins > 1 << 16) return fail(RT_ERR_INVALID_ARG, "n_bins must be in [1, 65536]");
+  if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(RT_ERR_NONFINITE, "histogram range");
+  if (!(hi > lo)) return fail(RT_ERR_INVALID_ARG, "hi must exceed lo");
+  void* work = nullptr;
+  RT_HIP(hipMallocAsync(&work, sizeof(double) * (n_bins + 8), stream));
+  RT_HIP(launch_histogram(n, mu, jac, 1, n_bins, lo, hi, pdf, moments, static_cast<double*>(work), stream));
   RT_HIP(hipFreeAsync(work, stream));
   return RT_OK;
 }

@@ -73,7 +73,7 @@ hipError_t launch_field_eval(DevCosmo c, const DevSet* set, bool fp64, int64_t n
                              double* grad, hipStream_t s);
 hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const double* rays, double* mu,
                                 double* jac, hipStream_t s);
-hipError_t launch_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
-                            double* pdf, double* moments, double* work, hipStream_t s);
+hipError_t launch_histogram(int64_t n, const double* mu, const double* jac, int mode, int32_t n_bins, double lo,
+                            double hi, double* pdf, double* moments, double* work, hipStream_t s);
 
 }  // namespace rt

@@ -560,15 +560,21 @@ __global__ __launch_bounds__(256) void magnification_kernel(double chi_s, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Source-weighted mu histogram (Sec. 5.3, eq. weighthisto), deterministic:
-// every sum runs in a fixed order (strided per thread, then a tree in LDS).
-// work layout: [n_bins] bin weights, then sum w, sum w mu, n_bad, n_under, n_over.
+// Source-weighted histograms (Sec. 5.3, eq. weighthisto; the same weighting
+// for the shear distribution of Sec. 5.4): every bundle with mu > 0 has
+// weight 1/mu.  mode 0: value log10 mu, bins of width in mu; mode 1: value
+// |gamma| from the Jacobian, bins of width in |gamma|.  Deterministic: every
+// sum runs in a fixed order (strided per thread, then a tree in LDS).
+// work layout: [n_bins] bin weights, then sum w, sum w v, n_bad, n_under, n_over.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int mu_bin(double m, double lo, double hi, int nb) {
-  const double lm = log10(m);
-  if (lm < lo) return -1;
-  if (lm >= hi) return nb;
-  int i = (int)floor((lm - lo) / (hi - lo) * nb);
+__device__ __forceinline__ double hist_value(int mode, const double* mu, const double* jac, int64_t n, int64_t i) {
+  return mode == 0 ? log10(mu[i]) : hypot(jac[n + i], jac[2 * n + i]);
+}
+
+__device__ __forceinline__ int value_bin(double v, double lo, double hi, int nb) {
+  if (v < lo) return -1;
+  if (v >= hi) return nb;
+  int i = (int)floor((v - lo) / (hi - lo) * nb);
   return i >= nb ? nb - 1 : i;
 }
 
@@ -586,20 +592,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void hist_bins_kernel(int64_t n, const double* mu, int32_t nb, double lo, double hi,
-                                                        double* work) {
+__global__ __launch_bounds__(256) void hist_bins_kernel(int64_t n, const double* mu, const double* jac, int mode,
+                                                        int32_t nb, double lo, double hi, double* work) {
   __shared__ double sh[256];
   const int bin = blockIdx.x;
   if (bin < nb) {
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) {
       const double m = mu[i];
-      if (m > 0.0 && mu_bin(m, lo, hi, nb) == bin) acc += 1.0 / m;
+      if (m > 0.0 && value_bin(hist_value(mode, mu, jac, n, i), lo, hi, nb) == bin) acc += 1.0 / m;
     }
     const double t = block_sum<256>(acc, sh);
     if (threadIdx.x == 0) work[bin] = t;
   } else {
-    double sw = 0.0, swm = 0.0, bad = 0.0, under = 0.0, over = 0.0;
+    double sw = 0.0, swv = 0.0, bad = 0.0, under = 0.0, over = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += 256) {
       const double m = mu[i];
       if (!(m > 0.0)) {
@@ -607,13 +613,14 @@ __global__ __launch_bounds__(256) void hist_bins_kernel(int64_t n, const double*
         continue;
       }
       const double w = 1.0 / m;
+      const double v = hist_value(mode, mu, jac, n, i);
       sw += w;
-      swm += w * m;
-      const int b = mu_bin(m, lo, hi, nb);
+      swv += w * (mode == 0 ? m : v);
+      const int b = value_bin(v, lo, hi, nb);
       if (b < 0) under += 1.0;
       if (b >= nb) over += 1.0;
     }
-    const double t0 = block_sum<256>(sw, sh), t1 = block_sum<256>(swm, sh), t2 = block_sum<256>(bad, sh);
+    const double t0 = block_sum<256>(sw, sh), t1 = block_sum<256>(swv, sh), t2 = block_sum<256>(bad, sh);
     const double t3 = block_sum<256>(under, sh), t4 = block_sum<256>(over, sh);
     if (threadIdx.x == 0) {
       work[nb] = t0;
@@ -625,20 +632,24 @@ __global__ __launch_bounds__(256) void hist_bins_kernel(int64_t n, const double*
   }
 }
 
-__global__ __launch_bounds__(256) void hist_final_kernel(int64_t n, const double* mu, int32_t nb, double lo, double hi,
-                                                         const double* work, double* pdf, double* moments) {
+__global__ __launch_bounds__(256) void hist_final_kernel(int64_t n, const double* mu, const double* jac, int mode,
+                                                         int32_t nb, double lo, double hi, const double* work,
+                                                         double* pdf, double* moments) {
   __shared__ double sh[256];
   const double sw = work[nb];
   const double mean = sw > 0.0 ? work[nb + 1] / sw : 0.0;
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     const double m = mu[i];
-    if (m > 0.0) acc += (1.0 / m) * (m - mean) * (m - mean);
+    if (m > 0.0) {
+      const double v = mode == 0 ? m : hist_value(mode, mu, jac, n, i);
+      acc += (1.0 / m) * (v - mean) * (v - mean);
+    }
   }
   const double var = block_sum<256>(acc, sh);
   for (int i = threadIdx.x; i < nb; i += 256) {
     const double e0 = lo + (hi - lo) * i / nb, e1 = lo + (hi - lo) * (i + 1) / nb;
-    const double width = pow(10.0, e1) - pow(10.0, e0);
+    const double width = mode == 0 ? pow(10.0, e1) - pow(10.0, e0) : (hi - lo) / nb;
     pdf[i] = sw > 0.0 ? work[i] / (sw * width) : 0.0;
   }
   if (threadIdx.x == 0) {
@@ -786,12 +797,13 @@ hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const d
   return hipGetLastError();
 }
 
-hipError_t launch_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi, double* pdf,
-                            double* moments, double* work, hipStream_t s) {
-  hipLaunchKernelGGL(hist_bins_kernel, dim3(n_bins + 1), dim3(256), 0, s, n, mu, n_bins, log_lo, log_hi, work);
+hipError_t launch_histogram(int64_t n, const double* mu, const double* jac, int mode, int32_t n_bins, double lo,
+                            double hi, double* pdf, double* moments, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(hist_bins_kernel, dim3(n_bins + 1), dim3(256), 0, s, n, mu, jac, mode, n_bins, lo, hi, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hist_final_kernel, dim3(1), dim3(256), 0, s, n, mu, n_bins, log_lo, log_hi, work, pdf, moments);
+  hipLaunchKernelGGL(hist_final_kernel, dim3(1), dim3(256), 0, s, n, mu, jac, mode, n_bins, lo, hi, work, pdf,
+                     moments);
   return hipGetLastError();
 }
 

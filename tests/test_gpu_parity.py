@@ -278,6 +278,14 @@ def test_magnification_and_histogram_parity():
     torch.cuda.synchronize()
     assert np.allclose(pdf.cpu().numpy(), ref_pdf, rtol=1e-12, atol=1e-14)
     assert np.allclose(mom.cpu().numpy(), ref_mom, rtol=1e-12, atol=0)
+    # shear PDF of the oracle-traced bundles' Jacobians
+    ref_pdf, ref_mom = orc.shear_histogram(o["mu"], o["jac"], 40, 0.0, 0.2)
+    pdf = torch.empty(40, dtype=torch.float64, device=dev)
+    rt.rt_shear_histogram(nb, torch.from_numpy(o["mu"]).to(dev), torch.from_numpy(o["jac"]).to(dev), 40, 0.0, 0.2,
+                          pdf, mom)
+    torch.cuda.synchronize()
+    assert np.allclose(pdf.cpu().numpy(), ref_pdf, rtol=1e-12, atol=1e-14)
+    assert np.allclose(mom.cpu().numpy(), ref_mom, rtol=1e-12, atol=0)
 
 
 def test_result_independent_of_grid_size():

@@ -138,3 +138,22 @@ def test_replica_selection_by_midpoint():
     assert list(ss) == [0, 0, 1, 1, 1, 2]
     # an exact tie (midpoint on a boundary) goes to the farther replica
     assert list(orc.replica_step_sets(np.array([0.0, 20.0]), 10.0, 3)) == [1]
+
+
+def test_shear_histogram_against_numpy():
+    """Source-weighted |gamma| histogram equals numpy's weighted histogram of hypot(g1, g2)."""
+    rng = np.random.default_rng(12)
+    n = 4000
+    mu = np.exp(rng.normal(0, 0.05, n))
+    mu[:3] = [-1.0, 0.0, 2.0]
+    jac = rng.normal(0, 0.02, (4, n))
+    pdf, mom = orc.shear_histogram(mu, jac, 50, 0.0, 0.08)
+    ok = mu > 0
+    g = np.hypot(jac[1], jac[2])[ok]
+    w = 1 / mu[ok]
+    h, edges = np.histogram(g, bins=50, range=(0.0, 0.08), weights=w)
+    assert np.allclose(pdf, h / (w.sum() * np.diff(edges)), rtol=1e-12, atol=0)
+    assert mom[0] == pytest.approx(w.sum(), rel=1e-13)
+    assert mom[1] == pytest.approx(np.sum(w * g) / w.sum(), rel=1e-12)
+    assert mom[2] == pytest.approx(math.sqrt(np.sum(w * (g - mom[1]) ** 2) / w.sum()), rel=1e-10)
+    assert mom[3] == 2 and mom[5] == np.sum(g >= 0.08)
