@@ -3,7 +3,7 @@
 Workload: the NFW halo (1e5 equal-mass particles from an NFW halo with
 M200 = 1e14 Msun, c = 5, truncated at r200, softening 2 kpc physical, z_l = 0.25,
 z_s = 0.5) with 256 x 256 bundles (anchor + 8 rays, radius 1e-3 arcsec) over
-+-3 r_s and 2000 fine RK4 steps across the halo (2237 steps in all).
++-3 r_s and 2000 fine RK4 steps across the halo (2236 steps in all).
 
 One step = one pass of the whole path over one batch of the bundle grid: a
 band of 7168 consecutive bundles (64 512 rays) of the row-major grid, sized to
@@ -13,18 +13,23 @@ construction, tracing with FP32 pair terms + Kahan sums and FP64 integration
 Steps walk through the grid band after band.  Inputs (particles, bundle
 directions) are resident in HBM before the timed region.
 
-Untimed: every second bundle of the first timed band is also traced in FP64
-(4096 bundles, enough to fill the GPU) to give the mixed-vs-FP64 mu error and
-the FP64 throughput; the CPU oracle is timed on two bundles of the batch (full
-schedule, all particles).
+Untimed: the bundles of the first timed batch are also traced in FP64 on the
+GPU, to give the mixed-vs-FP64 mu error and the FP64 throughput; the CPU oracle
+is timed on two bundles of the batch (full schedule, all particles).
+
+Other workloads (--workload), for the per-workload table of the design notes:
+point (32 x 32 bundles around a 1e12 Msun point lens, 1225 steps), box18 /
+box20 (Zel'dovich boxes of 2^18 / 2^20 particles in 14 replicas, 0.1 arcsec
+bundles, 2000 steps; one step = one band of --band bundles), batched (64 uneven
+fields traced in one launch, --side x --side bundles per field).
 
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -37,13 +42,13 @@ if ROOT not in sys.path:
 
 METRIC = "ray-particle interactions/s and bundles/s at μ err ≤1e-4 vs FP64 (mixed vs FP64)"
 PEAK_FP32 = 157.3      # TFLOP/s, MI355X FP32 vector (published)
-# HBM bytes per launch of the FP32 trace kernel on this workload, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and 1.0),
-# keyed by the sha256 prefix of the kernel source they were taken with.
-MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0,
-                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 PEAK_FP64 = 78.6       # TFLOP/s, MI355X FP64 vector (published)
 FLOP_PER_INTERACTION = 20.0
+# HBM bytes per launch of the FP32 trace kernel on the default workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and
+# 1.0), keyed by the sha256 prefix of the kernel source they were taken with.
+MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0,
+                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 
 def parse():
@@ -51,12 +56,15 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="nfw", choices=["nfw", "point", "box18", "box20", "batched"])
     p.add_argument("--band", type=int, default=7168,
-                   help="bundles per step: 7168 bundles = 1024 groups of 7 bundles, i.e. two full rounds of the "
-                        "512 workgroups that the trace kernel keeps resident on 256 CUs")
-    p.add_argument("--n-side", type=int, default=256)
-    p.add_argument("--n-part", type=int, default=100_000)
-    p.add_argument("--fp64-stride", type=int, default=2, help="every k-th bundle of one band traced in FP64")
+                   help="bundles per step of the single-field workloads (nfw, box18, box20): 7168 bundles = "
+                        "1024 groups of 7 bundles, two full rounds of the 512 workgroups that the trace kernel "
+                        "keeps resident on 256 CUs")
+    p.add_argument("--side", type=int, default=16, help="bundle grid side of each field of the batched workload")
+    p.add_argument("--precision", default="fp32k", choices=["fp32k", "fp64"])
+    p.add_argument("--fp64-stride", type=int, default=1,
+                   help="every k-th bundle of the first timed batch is traced again in FP64")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-autotune", action="store_true")
@@ -67,14 +75,13 @@ def parse():
     return p.parse_args()
 
 
-def traffic_bytes(band):
+def traffic_bytes(a):
     """Measured HBM bytes per trace launch, or None when the kernel source has changed
-    since the counters were taken (or the batch differs from the profiled one)."""
-    import hashlib
+    since the counters were taken or the launch differs from the profiled one."""
     src = os.path.join(ROOT, "paper_1110_4894_amd", "csrc", "rt_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     m = MEASURED_TRAFFIC.get(sha)
-    if m is None or band != 7168:
+    if m is None or a.workload != "nfw" or a.band != 7168 or a.precision != "fp32k":
         return None
     return m["read"] + m["write"]
 
@@ -89,6 +96,41 @@ def mu_stats(mu, ref):
             "max_rel_weak": float(rel[weak].max()) if weak.any() else 0.0,
             "max_cond": float(cond.max()), "max_inv_mu": float(np.max(np.abs(1 / mu - 1 / ref))),
             "n": int(mu.size), "n_weak": int(weak.sum()), "max_abs_mu": float(np.abs(ref).max())}
+
+
+def build_workload(a):
+    from paper_1110_4894_amd import workloads
+    if a.workload == "nfw":
+        return workloads.nfw(), ("nfw-halo 1e5 particles (M200 1e14 Msun, c 5, z_l 0.25, z_s 0.5), 256x256 "
+                                 "bundles over +-3 r_s, r_b 1e-3 arcsec, 2000 fine RK4 steps")
+    if a.workload == "point":
+        return workloads.schwarzschild(), ("point lens 1e12 Msun at z_l 0.25, z_s 0.5, 32x32 bundles at "
+                                           "0.5-10 theta_E, r_b 1e-3 arcsec, 1000 fine RK4 steps")
+    if a.workload in ("box18", "box20"):
+        n, side = (18, 128) if a.workload == "box18" else (20, 512)
+        return workloads.box(n_part_log2=n, n_side=side), (
+            "Zel'dovich box 2^%d particles, 100 Mpc/h, 14 replicas to z_s 0.5, %dx%d bundles over 1 deg, "
+            "r_b 0.1 arcsec, 2000 RK4 steps, softening 50 kpc/h" % (n, side, side))
+    return workloads.batched(side_override=a.side), (
+        "64 uneven fields (16 point-mass groups, 32 NFW haloes of 1e4-1e6 particles, 16 box sub-volumes), "
+        "%dx%d bundles per field, r_b 0.1 arcsec, 500 fine RK4 steps per field, one launch" % (a.side, a.side))
+
+
+def batches(w, a):
+    """Per-step workloads sharing the particle sets: consecutive bands of the row-major
+    bundle grid (wrapping at its end) for one-field workloads, else the whole workload."""
+    from paper_1110_4894_amd import workloads
+    if a.workload in ("point", "batched"):
+        return [w], w.n_bundles
+    f = w.fields[0]
+    nb_all = f.n_bundles
+    band = min(a.band, nb_all)
+    out = []
+    for i in range(-(-nb_all // band)):
+        th = np.ascontiguousarray(f.theta[:, np.arange(i * band, (i + 1) * band) % nb_all])
+        out.append(workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
+                                      [workloads.FieldSpec(f.name, f.sets, th, f.schedule, f.replica_box, {})]))
+    return out, band
 
 
 def main():
@@ -113,42 +155,34 @@ def main():
         print(json.dumps({"copy_bytes": 4 * n}), flush=True)
         return
     rt.load()
+    prec = rt.RT_FP64 if a.precision == "fp64" else rt.RT_FP32_KAHAN
 
     t_setup = time.time()
-    w = workloads.nfw(n_side=a.n_side, n_part=a.n_part)
-    f = w.fields[0]
-    nb_all = f.n_bundles
-    band = a.band
-    n_bands = -(-nb_all // band)
-    # consecutive bands of the row-major bundle grid, wrapping around at its end
-    bands = [np.ascontiguousarray(f.theta[:, (np.arange(i * band, (i + 1) * band) % nb_all)])
-             for i in range(n_bands)]
-    w_batch = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
-                                 [workloads.FieldSpec(f.name, f.sets, bands[0], f.schedule, f.replica_box, {})])
+    w, desc = build_workload(a)
+    steps_w, per_step = batches(w, a)
     uploads = {}
-    g = GpuRun(w_batch, uploads=uploads)
-    theta_dev = [torch.from_numpy(b).to(dev) for b in bands]
-    stream = torch.cuda.current_stream()
-    n_steps_path = g.max_steps
+    g = GpuRun(steps_w[0], uploads=uploads)
+    thetas = [torch.from_numpy(np.ascontiguousarray(np.concatenate([f.theta for f in sw.fields], axis=1))).to(dev)
+              for sw in steps_w]
+    n_rk = g.max_steps
     inter_per_step = g.interactions()
-    print("setup: %d bundles per step, %d RK4 steps, %d particles, %.3e interactions per step (%.1f s)"
-          % (band, n_steps_path, a.n_part, inter_per_step, time.time() - t_setup), file=sys.stderr, flush=True)
+    n_part = max(sum(s.xyz.shape[0] for s in f.sets) for f in w.fields)
+    print("setup: %s, %d bundles per step, %d RK4 steps (longest field), %.3e interactions per step (%.1f s)"
+          % (a.workload, per_step, n_rk, inter_per_step, time.time() - t_setup), file=sys.stderr, flush=True)
 
     tuned = None
     if a.plan >= 0:
-        rt.rt_force_plan(rt.RT_FP32_KAHAN, a.plan)
+        rt.rt_force_plan(prec, a.plan)
         tuned = a.plan
     elif not a.no_autotune:
         g.build_bundles()
-        mid = n_steps_path // 2
-        tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, rt.RT_FP32_KAHAN, mid, 6, g.n_bundles, g.rays)
-        print("autotune: plan %d %s" % (tuned, rt.rt_plan_describe(rt.RT_FP32_KAHAN, tuned)), file=sys.stderr,
-              flush=True)
+        tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, prec, n_rk // 2, 6, g.n_bundles, g.rays)
+        print("autotune: plan %d %s" % (tuned, rt.rt_plan_describe(prec, tuned)), file=sys.stderr, flush=True)
 
     def one_step(i):
-        g.set_theta(theta_dev[i % n_bands])
+        g.set_theta(thetas[i % len(thetas)])
         g.build_bundles()
-        g.trace(rt.RT_FP32_KAHAN)
+        g.trace(prec)
         g.magnification()
         return g.histogram()
 
@@ -159,95 +193,104 @@ def main():
         print("warmup step %d done" % i, file=sys.stderr, flush=True)
 
     kernel_ms = []
-    mu32 = {}
+    mu_first = None
+    first = a.warmup % len(thetas)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
         one_step(a.warmup + i)
         info = rt.rt_last_trace_info()      # waits for this step's trace graph (events on its stream)
         kernel_ms.append(info["kernel_ms"])
-        mu32[(a.warmup + i) % n_bands] = g.mu.clone()
-        print("step %d: trace %.1f ms, plan %d, grid %d, graph reused %d" % (
-            i, info["kernel_ms"], info["plan_id"], info["grid_blocks"], info["graph_reused"]), file=sys.stderr,
-            flush=True)
+        if i == 0:
+            mu_first = g.mu.clone()
+        print("step %d: trace %.1f ms, plan %d, grid %d, items %d, graph reused %d" % (
+            i, info["kernel_ms"], info["plan_id"], info["grid_blocks"], info["n_items"], info["graph_reused"]),
+            file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rt.rt_enable_timing(False)
     elapsed = t1 - t0
-    total_inter = inter_per_step * a.steps
-    value = total_inter / elapsed
-    bundles_per_s = band * a.steps / elapsed
-    ms_per_step = 1e3 * elapsed / a.steps
+    value = inter_per_step * a.steps / elapsed
     k_ms = float(np.mean(kernel_ms))
     achieved = FLOP_PER_INTERACTION * inter_per_step / (k_ms * 1e-3) / 1e12
+    peak = PEAK_FP64 if prec == rt.RT_FP64 else PEAK_FP32
+    prec_name = "fp64" if prec == rt.RT_FP64 else "fp32-kahan field, fp64 integration"
     result = {
         "metric": METRIC, "value": value, "unit": "ray-particle interactions/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "nfw-halo 1e5 particles (M200 1e14 Msun, c 5, z_l 0.25, z_s 0.5), 256x256 "
-                               "bundles over +-3 r_s, r_b 1e-3 arcsec, 2000 fine RK4 steps (%d in all); "
-                               "one step = one band of %d consecutive bundles" % (n_steps_path, band),
-                   "bundles_per_step": band, "rays_per_step": 9 * band, "rk4_steps": n_steps_path,
-                   "particles": a.n_part, "precision": "fp32-kahan field, fp64 integration",
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == rt.RT_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "%s (%d RK4 steps in the longest field); one step = %d bundles"
+                               % (desc, n_rk, per_step),
+                   "name": a.workload, "bundles_per_step": per_step, "rays_per_step": 9 * per_step,
+                   "rk4_steps": n_rk, "particles": n_part, "precision": prec_name,
                    "parallelism": "single GPU", "plan": tuned},
-        "bundles_per_s": bundles_per_s,
+        "bundles_per_s": per_step * a.steps / elapsed,
         "interactions_per_step": inter_per_step,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": traffic_bytes(band),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic_bytes(a),
                      "traffic_unit": "HBM bytes per launch (read + write)",
-                     "kernel": "trace_kernel (fp32)", "kernel_ms": k_ms,
-                     "flop_per_interaction": FLOP_PER_INTERACTION},
+                     "kernel": "trace_kernel (%s)" % ("fp64" if prec == rt.RT_FP64 else "fp32"),
+                     "kernel_ms": k_ms, "flop_per_interaction": FLOP_PER_INTERACTION},
     }
 
-    # ---------------------------------------------------------------- FP64 reference on a subsample
-    if not a.no_fp64:
-        errs = []
-        f64_ms, f64_inter = [], 0.0
-        for bi, m32 in sorted(mu32.items())[:1]:
-            sub = np.ascontiguousarray(bands[bi][:, ::a.fp64_stride])
-            ws = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
-                                    [workloads.FieldSpec(f.name, f.sets, sub, f.schedule, f.replica_box, {})])
-            gs = GpuRun(ws, uploads=uploads)
-            gs.build_bundles()
-            rt.rt_enable_timing(True)
-            gs.trace(rt.RT_FP64)
-            info = rt.rt_last_trace_info()
-            rt.rt_enable_timing(False)
-            gs.magnification()
-            torch.cuda.synchronize()
-            f64_ms.append(info["kernel_ms"])
-            f64_inter += gs.interactions()
-            errs.append((m32.cpu().numpy()[::a.fp64_stride], gs.mu.cpu().numpy()))
-        m32c = np.concatenate([e[0] for e in errs])
-        m64c = np.concatenate([e[1] for e in errs])
-        result["mu_err_vs_fp64"] = mu_stats(m32c, m64c)
-        fp64_rate = f64_inter / (sum(f64_ms) * 1e-3)
-        result["fp64"] = {"interactions_per_s": fp64_rate, "bundles": int(m64c.size),
-                          "tflops": FLOP_PER_INTERACTION * fp64_rate / 1e12,
-                          "frac_of_fp64_peak": FLOP_PER_INTERACTION * fp64_rate / 1e12 / PEAK_FP64,
-                          "mixed_speedup": (FLOP_PER_INTERACTION * inter_per_step / (k_ms * 1e-3)) /
-                                           (FLOP_PER_INTERACTION * fp64_rate)}
+    # ---------------------------------------------------------------- FP64 reference on the first batch
+    if not a.no_fp64 and prec != rt.RT_FP64:
+        sw = steps_w[first]
+        sub = [workloads.FieldSpec(f.name, f.sets, np.ascontiguousarray(f.theta[:, ::a.fp64_stride]),
+                                   f.schedule, f.replica_box, {}) for f in sw.fields]
+        gs = GpuRun(workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius, sub), uploads=uploads)
+        gs.build_bundles()
+        rt.rt_enable_timing(True)
+        gs.trace(rt.RT_FP64)
+        info = rt.rt_last_trace_info()
+        rt.rt_enable_timing(False)
+        gs.magnification()
+        torch.cuda.synchronize()
+        off = np.cumsum([0] + [f.n_bundles for f in sw.fields])
+        m_all = mu_first.cpu().numpy()
+        m32 = np.concatenate([m_all[o:o + f.n_bundles][::a.fp64_stride] for o, f in zip(off, sw.fields)])
+        m64 = gs.mu.cpu().numpy()
+        result["mu_err_vs_fp64"] = mu_stats(m32, m64)
+        rate64 = gs.interactions() / (info["kernel_ms"] * 1e-3)
+        result["fp64"] = {"interactions_per_s": rate64, "bundles": int(m64.size), "kernel_ms": info["kernel_ms"],
+                          "tflops": FLOP_PER_INTERACTION * rate64 / 1e12,
+                          "frac_of_fp64_peak": FLOP_PER_INTERACTION * rate64 / 1e12 / PEAK_FP64,
+                          "mixed_speedup": (inter_per_step / (k_ms * 1e-3)) / rate64}
         print("fp64 reference: %s" % json.dumps(result["mu_err_vs_fp64"]), file=sys.stderr, flush=True)
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
         import oracle as orc
         from tests.oracle_run import oracle_fields
-        sub = np.ascontiguousarray(bands[0][:, : a.cpu_bundles * 37: 37][:, : a.cpu_bundles])
-        ws = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
-                                [workloads.FieldSpec(f.name, f.sets, sub, f.schedule, f.replica_box, {})])
-        c, chi_s, fields, theta = oracle_fields(ws)
-        rays = orc.build_bundles(c, fields, theta, ws.bundle_radius)
+        sw = steps_w[first]
+        if a.workload == "batched":
+            # one bundle from each of the cheapest fields
+            cost = [sum(s.xyz.shape[0] for s in f.sets) for f in sw.fields]
+            pick = sorted(range(len(sw.fields)), key=lambda i: cost[i])[: 3 * a.cpu_bundles]
+            fields = [workloads.FieldSpec(sw.fields[i].name, sw.fields[i].sets,
+                                          np.ascontiguousarray(sw.fields[i].theta[:, :1]), sw.fields[i].schedule,
+                                          sw.fields[i].replica_box, {}) for i in pick]
+        else:
+            f = sw.fields[0]
+            fields = [workloads.FieldSpec(f.name, f.sets,
+                                          np.ascontiguousarray(f.theta[:, ::37][:, :a.cpu_bundles]),
+                                          f.schedule, f.replica_box, {})]
+        ws = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius, fields)
+        c, chi_s, ofields, theta = oracle_fields(ws)
+        rays = orc.build_bundles(c, ofields, theta, ws.bundle_radius)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
         tc0 = time.perf_counter()
-        orc.trace(c, fields, rays, n_threads=threads)
+        orc.trace(c, ofields, rays, n_threads=threads)
         tc = time.perf_counter() - tc0
-        n_inter = 9.0 * sub.shape[1] * 4.0 * sum(len(s.xyz) for s in f.sets) * n_steps_path
+        n_inter = 0.0
+        for of in ofields:
+            npart = np.array([len(of.sets[s].m) if s >= 0 else 0 for s in of.step_set], dtype=np.float64)
+            n_inter += 9.0 * of.n_bundles * 4.0 * npart.sum()
         result["cpu_baseline"] = {"value": n_inter / tc, "unit": "ray-particle interactions/s", "cores": threads,
                                   "kind": "oracle", "seconds": tc,
-                                  "sample": "%d bundles (%d rays) of the first band, full %d-step schedule, all %d "
-                                            "particles, FP64" % (sub.shape[1], 9 * sub.shape[1], n_steps_path,
-                                                                 a.n_part)}
+                                  "sample": "%d bundles (%d rays) of the first timed batch, full schedules and "
+                                            "particle sets, FP64" % (ws.n_bundles, 9 * ws.n_bundles)}
     print(json.dumps(result), flush=True)
 
 
