@@ -203,6 +203,7 @@ def main():
         kernel_ms.append(info["kernel_ms"])
         if i == 0:
             mu_first = g.mu.clone()
+            rays_first = g.rays.clone()
         print("step %d: trace %.1f ms, plan %d, grid %d, items %d, graph reused %d" % (
             i, info["kernel_ms"], info["plan_id"], info["grid_blocks"], info["n_items"], info["graph_reused"]),
             file=sys.stderr, flush=True)
@@ -252,6 +253,20 @@ def main():
         m32 = np.concatenate([m_all[o:o + f.n_bundles][::a.fp64_stride] for o, f in zip(off, sw.fields)])
         m64 = gs.mu.cpu().numpy()
         result["mu_err_vs_fp64"] = mu_stats(m32, m64)
+        # exit positions: |dx| relative to the deflection |x - theta chi_s| of the FP64 run
+        bidx = np.concatenate([o + np.arange(f.n_bundles)[::a.fp64_stride] for o, f in zip(off, sw.fields)])
+        ridx = (9 * bidx[:, None] + np.arange(9)).ravel()
+        r32 = rays_first.cpu().numpy()[:, ridx]
+        r64 = gs.rays.cpu().numpy()
+        th = np.repeat(np.concatenate([f.theta[:, ::a.fp64_stride] for f in sw.fields], axis=1), 9, axis=1)
+        ang = np.tile(np.concatenate([[0.0], np.arange(8) * np.pi / 4]), bidx.size)
+        ring = np.tile(np.concatenate([[0.0], np.ones(8)]), bidx.size) * w.bundle_radius
+        thx, thy = th[0] + ring * np.cos(ang), th[1] + ring * np.sin(ang)
+        defl = np.hypot(r64[1] - thx * gs.chi_s, r64[2] - thy * gs.chi_s)
+        dx = np.hypot(r32[1] - r64[1], r32[2] - r64[2])
+        result["exit_err_vs_fp64"] = {"max_rel_deflection": float(np.max(dx / (defl + 1e-12))),
+                                      "p50_rel_deflection": float(np.median(dx / (defl + 1e-12))),
+                                      "max_abs_mpc": float(dx.max())}
         rate64 = gs.interactions() / (info["kernel_ms"] * 1e-3)
         result["fp64"] = {"interactions_per_s": rate64, "bundles": int(m64.size), "kernel_ms": info["kernel_ms"],
                           "tflops": FLOP_PER_INTERACTION * rate64 / 1e12,

@@ -1,0 +1,147 @@
+"""Particle-mesh field of Sec. 3.3 and the interpolation scheme of App. B, in plain
+FP64 numpy.
+
+TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``: only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use it.
+It shares no code with the product library.
+
+What is computed (isolated lenses, the zero-padded case of Sec. 3.3):
+
+1. Cloud-in-Cell deposit of the particle masses onto the n^3 nodes
+   x_ijk = origin + h (i, j, k) of a cubic grid (Sec. 3.3).  Mass whose cloud
+   falls outside the grid is dropped.
+2. The potential and its three derivatives at the nodes, by convolving the node
+   masses with the Plummer kernels of eq. psi and eq. derivs on a grid
+   zero-padded to (2n)^3, so that the FFT product is the exact linear
+   convolution:  phi = -(G/c^2) sum_n' M_n' (d^2 + eps^2)^(-1/2) and
+   dphi/dx = (G/c^2) sum_n' M_n' d_x (d^2 + eps^2)^(-3/2), d = x_n - x_n'.
+   With eps = 0 the self term (d = 0) is left out.
+3. App. B: natural cubic-spline second derivatives of each grid along the line
+   of sight x^3, once per grid; at a point, (2 n_int)^2 spline evaluations along
+   x^3, then 2 n_int local natural splines along x^1 through those values, then
+   one local natural spline along x^2.  The local windows hold n_int nodes on
+   each side of the point, shifted inwards at the grid's edges; outside the
+   node range the field is zero.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.linalg import solve_banded
+
+from . import G_over_c2
+
+
+def cic_deposit(xyz: np.ndarray, m: np.ndarray, origin, h: float, n: int) -> np.ndarray:
+    """Node masses [n, n, n] (index order x^1, x^2, x^3) by Cloud-in-Cell (Sec. 3.3)."""
+    u = (np.asarray(xyz, dtype=np.float64) - np.asarray(origin, dtype=np.float64)) / h
+    i0 = np.floor(u).astype(np.int64)
+    f = u - i0
+    grid = np.zeros((n, n, n))
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                w = ((f[:, 0] if a else 1 - f[:, 0]) * (f[:, 1] if b else 1 - f[:, 1]) *
+                     (f[:, 2] if c else 1 - f[:, 2]))
+                idx = i0 + np.array([a, b, c])
+                ok = np.all((idx >= 0) & (idx < n), axis=1)
+                np.add.at(grid, (idx[ok, 0], idx[ok, 1], idx[ok, 2]), (m * w)[ok])
+    return grid
+
+
+def isolated_field(mass: np.ndarray, h: float, eps: float) -> np.ndarray:
+    """[4, n, n, n]: phi, dphi/dx^1, dphi/dx^2, dphi/dx^3 at the nodes (eq. psi, derivs),
+    by FFT convolution on the zero-padded (2n)^3 grid (Sec. 3.3)."""
+    n = mass.shape[0]
+    M = 2 * n
+    G = G_over_c2()
+    d = np.arange(M)
+    d = np.where(d < n, d, d - M) * h           # displacement of padded index i (index n unused)
+    dx, dy, dz = np.meshgrid(d, d, d, indexing="ij")
+    r2 = dx * dx + dy * dy + dz * dz + eps * eps
+    with np.errstate(divide="ignore"):
+        k1 = np.where(r2 > 0, 1.0 / np.sqrt(r2), 0.0)
+    k3 = k1 ** 3
+    kernels = [-G * k1, G * dx * k3, G * dy * k3, G * dz * k3]
+    padded = np.zeros((M, M, M))
+    padded[:n, :n, :n] = mass
+    fm = np.fft.fftn(padded)
+    out = np.empty((4, n, n, n))
+    for q, K in enumerate(kernels):
+        out[q] = np.real(np.fft.ifftn(fm * np.fft.fftn(K)))[:n, :n, :n]
+    return out
+
+
+def spline_y2_line(y: np.ndarray, h: float) -> np.ndarray:
+    """Natural cubic-spline second derivatives through equally spaced values y[..., k]
+    (App. B; y2 = 0 at both ends, y2[k-1] + 4 y2[k] + y2[k+1] = 6 (y[k+1] - 2 y[k] + y[k-1]) / h^2)."""
+    m = y.shape[-1]
+    lead = y.shape[:-1]
+    y2 = np.zeros_like(y)
+    if m < 3:
+        return y2
+    rhs = 6.0 * (y[..., 2:] - 2.0 * y[..., 1:-1] + y[..., :-2]) / (h * h)
+    ab = np.zeros((3, m - 2))
+    ab[0, 1:] = 1.0
+    ab[1, :] = 4.0
+    ab[2, :-1] = 1.0
+    sol = solve_banded((1, 1), ab, rhs.reshape(-1, m - 2).T)
+    y2[..., 1:-1] = sol.T.reshape(lead + (m - 2,))
+    return y2
+
+
+def spline_eval(yk, yk1, y2k, y2k1, A, h):
+    """Cubic spline between two nodes (App. B); A = (x_{k+1} - x) / h."""
+    B = 1.0 - A
+    return A * yk + B * yk1 + ((A ** 3 - A) * y2k + (B ** 3 - B) * y2k1) * (h * h) / 6.0
+
+
+def z_second_derivatives(fields: np.ndarray, h: float) -> np.ndarray:
+    """The once-per-grid spline of App. B along x^3, for each of the four grids."""
+    return spline_y2_line(fields, h)
+
+
+def _window(u: float, n: int, n_int: int):
+    k = min(max(int(np.floor(u)), 0), n - 2)
+    start = min(max(k - n_int + 1, 0), n - 2 * n_int)
+    return np.arange(start, start + 2 * n_int)
+
+
+def _local_spline(nodes: np.ndarray, vals: np.ndarray, u: float, h: float) -> float:
+    """Natural cubic spline through vals at integer nodes (spacing h), evaluated at u."""
+    y2 = spline_y2_line(vals, h)
+    k = min(max(int(np.floor(u)) - nodes[0], 0), len(nodes) - 2)
+    A = (nodes[0] + k + 1) - u
+    return spline_eval(vals[k], vals[k + 1], y2[k], y2[k + 1], A, h)
+
+
+def appb_eval(fields: np.ndarray, fields_y2z: np.ndarray, origin, h: float, n_int: int, p) -> np.ndarray:
+    """The four grid quantities at point p by the scheme of App. B; zero outside the nodes."""
+    n = fields.shape[1]
+    u = (np.asarray(p, dtype=np.float64) - np.asarray(origin, dtype=np.float64)) / h
+    if np.any(u < 0) or np.any(u > n - 1):
+        return np.zeros(4)
+    wx, wy = _window(u[0], n, n_int), _window(u[1], n, n_int)
+    kz = min(int(np.floor(u[2])), n - 2)
+    Az = (kz + 1) - u[2]
+    out = np.empty(4)
+    for q in range(4):
+        F, F2 = fields[q], fields_y2z[q]
+        # step 1: along x^3 on the (2 n_int)^2 lines of the window
+        v = np.empty((2 * n_int, 2 * n_int))
+        for a, i in enumerate(wx):
+            for b, j in enumerate(wy):
+                v[a, b] = spline_eval(F[i, j, kz], F[i, j, kz + 1], F2[i, j, kz], F2[i, j, kz + 1], Az, h)
+        # steps 2-3: local splines along x^1, one per x^2 node of the window
+        w = np.array([_local_spline(wx, v[:, b], u[0], h) for b in range(2 * n_int)])
+        # steps 4-5: one local spline along x^2
+        out[q] = _local_spline(wy, w, u[1], h)
+    return out
+
+
+def pm_field(xyz, m, eps, origin, h, n, n_int, points):
+    """phi [P] and grad [3, P] of the particle-mesh field at points [3, P]."""
+    fields = isolated_field(cic_deposit(xyz, m, origin, h, n), h, eps)
+    y2 = z_second_derivatives(fields, h)
+    pts = np.asarray(points, dtype=np.float64)
+    res = np.array([appb_eval(fields, y2, origin, h, n_int, pts[:, i]) for i in range(pts.shape[1])]).T
+    return res[0], res[1:]

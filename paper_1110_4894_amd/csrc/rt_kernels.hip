@@ -46,6 +46,18 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
   s = t;
 }
 
+// FP64 reciprocal square root of a finite x > 0: the hardware estimate r
+// (relative error about 2^-24) refined with the second-order expansion of
+// (1 - e)^(-1/2), where e = 1 - x r^2:  r (1 + e/2 + 3 e^2/8).  The neglected
+// term is 5 e^3 / 16, far below 2^-53.  The input is r^2 + eps^2 of a pair;
+// it is zero only for a ray exactly on an unsoftened particle, where the
+// field is singular anyway (the result is then NaN and the ray is flagged).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * r), r, 1.0);
+  return fma(r * e, fma(0.375, e, 0.5), r);
+}
+
 // ---------------------------------------------------------------------------
 // Background: a(t) of eq. scalefac2 (t = lookback time) and da/dt.
 // ---------------------------------------------------------------------------
@@ -232,7 +244,7 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, 
       double r2 = fma(ex, ex, e2);
       r2 = fma(ey, ey, r2);
       r2 = fma(ez, ez, r2);
-      const double ri = rsqrt(r2);
+      const double ri = rsqrt_f64(r2);
       const double mr = c.w * ri;
       a0 += mr;
       const double mr3 = mr * ri * ri;

@@ -1,0 +1,147 @@
+"""Pins of the oracle's particle-mesh field (Sec. 3.3) and App. B interpolation."""
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import CubicSpline
+
+import oracle as orc
+from oracle import pm
+
+
+def test_cic_conserves_mass_and_centre_of_mass():
+    """Linear CIC weights put a particle's mass on 8 nodes with its exact centre of mass."""
+    rng = np.random.default_rng(3)
+    n, h, origin = 12, 0.25, np.array([-1.0, 2.0, 10.0])
+    xyz = origin + rng.uniform(0.5, n - 1.5, (200, 3)) * h
+    m = rng.uniform(1.0, 5.0, 200)
+    g = pm.cic_deposit(xyz, m, origin, h, n)
+    assert g.sum() == pytest.approx(m.sum(), rel=1e-14)
+    idx = np.indices((n, n, n)).reshape(3, -1).T * h + origin
+    com = (g.reshape(-1)[:, None] * idx).sum(0) / g.sum()
+    assert np.allclose(com, (m[:, None] * xyz).sum(0) / m.sum(), rtol=0, atol=1e-12)
+    # a particle on a node deposits there only; one outside loses its mass
+    g1 = pm.cic_deposit(np.array([origin + h * np.array([3, 4, 5])]), np.array([2.0]), origin, h, n)
+    assert g1[3, 4, 5] == 2.0 and np.count_nonzero(g1) == 1
+    g2 = pm.cic_deposit(np.array([origin - 5 * h]), np.array([2.0]), origin, h, n)
+    assert g2.sum() == 0.0
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.07])
+def test_isolated_field_is_the_direct_sum_over_node_masses(eps):
+    """The zero-padded FFT convolution equals the brute-force Plummer sum over nodes."""
+    rng = np.random.default_rng(1)
+    n, h = 5, 0.3
+    mass = rng.uniform(0.0, 1e12, (n, n, n)) * (rng.random((n, n, n)) < 0.4)
+    f = pm.isolated_field(mass, h, eps)
+    G = orc.G_over_c2()
+    nodes = np.indices((n, n, n)).reshape(3, -1).T * h
+    M = mass.reshape(-1)
+    for t in rng.choice(n ** 3, 12, replace=False):
+        d = nodes[t] - nodes
+        r2 = (d * d).sum(1) + eps * eps
+        keep = r2 > 0
+        phi = -G * np.sum(M[keep] / np.sqrt(r2[keep]))
+        grad = G * np.sum((M[keep] * r2[keep] ** -1.5)[:, None] * d[keep], axis=0)
+        i, j, k = np.unravel_index(t, (n, n, n))
+        scale = G * M.sum() / h
+        assert abs(f[0, i, j, k] - phi) < 1e-12 * scale
+        assert np.allclose(f[1:, i, j, k], grad, rtol=0, atol=1e-12 * scale / h)
+
+
+def test_spline_second_derivatives_are_the_natural_spline():
+    rng = np.random.default_rng(4)
+    y = rng.normal(size=(3, 17))
+    h = 0.4
+    y2 = pm.spline_y2_line(y, h)
+    x = np.arange(17) * h
+    for r in range(3):
+        assert np.allclose(y2[r], CubicSpline(x, y[r], bc_type="natural")(x, 2), rtol=0, atol=1e-10)
+
+
+def _grid_of(fn, n, h, origin):
+    i = np.arange(n) * h
+    X, Y, Z = np.meshgrid(origin[0] + i, origin[1] + i, origin[2] + i, indexing="ij")
+    return fn(X, Y, Z)
+
+
+@pytest.mark.parametrize("n_int", [1, 2, 3])
+def test_appb_exact_on_nodes_and_for_linear_fields(n_int):
+    n, h, origin = 10, 0.5, np.array([1.0, -2.0, 3.0])
+    lin = lambda X, Y, Z: 0.3 + 1.5 * X - 0.7 * Y + 2.0 * Z
+    F = np.stack([_grid_of(lin, n, h, origin)] * 4)
+    F2 = pm.z_second_derivatives(F, h)
+    rng = np.random.default_rng(n_int)
+    for _ in range(20):
+        p = origin + rng.uniform(0, n - 1, 3) * h
+        assert np.allclose(pm.appb_eval(F, F2, origin, h, n_int, p), lin(*p), rtol=0, atol=1e-12)
+    G = np.stack([np.random.default_rng(9).normal(size=(n, n, n))] * 4)
+    G2 = pm.z_second_derivatives(G, h)
+    for ijk in [(0, 0, 0), (3, 4, 5), (9, 9, 9), (9, 0, 4)]:
+        p = origin + h * np.array(ijk)
+        assert np.allclose(pm.appb_eval(G, G2, origin, h, n_int, p), G[0][ijk], rtol=0, atol=1e-12)
+    # outside the nodes the field is zero
+    assert np.all(pm.appb_eval(G, G2, origin, h, n_int, origin - 0.1 * h) == 0)
+
+
+def test_appb_reduces_to_one_dimensional_natural_splines():
+    """A field varying along x^1 only is the local natural spline through the window's
+    2 n_int nodes; one varying along x^3 only is the natural spline through the whole line."""
+    n, h, origin = 12, 0.2, np.zeros(3)
+    rng = np.random.default_rng(7)
+    fx = rng.normal(size=n)
+    fz = rng.normal(size=n)
+    Fx = np.broadcast_to(fx[:, None, None], (n, n, n)).copy()
+    Fz = np.broadcast_to(fz[None, None, :], (n, n, n)).copy()
+    for n_int in (2, 3):
+        for u in [0.3, 2.5, 5.7, 10.9]:
+            p = np.array([u, 4.2, 6.6]) * h
+            got = pm.appb_eval(np.stack([Fx] * 4), pm.z_second_derivatives(np.stack([Fx] * 4), h), origin, h,
+                               n_int, p)[0]
+            k = min(int(u), n - 2)
+            start = min(max(k - n_int + 1, 0), n - 2 * n_int)
+            nodes = np.arange(start, start + 2 * n_int)
+            want = CubicSpline(nodes * h, fx[nodes], bc_type="natural")(u * h)
+            assert got == pytest.approx(float(want), abs=1e-12)
+            p = np.array([4.2, 6.6, u]) * h
+            got = pm.appb_eval(np.stack([Fz] * 4), pm.z_second_derivatives(np.stack([Fz] * 4), h), origin, h,
+                               n_int, p)[0]
+            want = CubicSpline(np.arange(n) * h, fz, bc_type="natural")(u * h)
+            assert got == pytest.approx(float(want), abs=1e-12)
+
+
+def test_appb_converges_and_improves_with_n_int():
+    """The local natural splines of App. B carry the O(h^2) end error of a natural spline
+    into the window's centre, damped by about 0.27 per node: halving the spacing divides
+    the error by ~4 (asymptotically), and every extra node per side lowers it."""
+    fn = lambda X, Y, Z: np.sin(1.3 * X) * np.cos(0.9 * Y) * np.sin(0.7 * Z + 0.2)
+    rng = np.random.default_rng(11)
+    pts = rng.uniform(2.0, 3.0, (30, 3))
+    errs = {}
+    for n, h in [(51, 0.1), (101, 0.05)]:
+        F = np.stack([_grid_of(fn, n, h, np.zeros(3))] * 4)
+        F2 = pm.z_second_derivatives(F, h)
+        for n_int in (1, 2, 3):
+            errs[h, n_int] = max(abs(pm.appb_eval(F, F2, np.zeros(3), h, n_int, p)[0] - fn(*p)) for p in pts)
+    for n_int in (1, 2, 3):
+        assert 3.2 < errs[0.1, n_int] / errs[0.05, n_int] < 5.0
+    assert errs[0.1, 1] > 3 * errs[0.1, 2] > 9 * errs[0.1, 3]
+
+
+def test_pm_field_of_a_compact_cloud_far_away_is_the_direct_sum():
+    """Outside a compact cloud the CIC smoothing is a small near-field effect: the PM field a
+    few cells away agrees with the direct Plummer sum over the particles."""
+    rng = np.random.default_rng(5)
+    n, h = 32, 0.05
+    origin = np.array([-0.8, -0.8, 99.2])
+    xyz = np.array([0.0, 0.0, 100.0]) + rng.normal(size=(300, 3)) * 0.05
+    m = np.full(300, 1e10)
+    eps = 0.01
+    pts = np.array([[0.45, 0.1, 100.2], [-0.5, -0.4, 99.7], [0.1, 0.52, 100.5]]).T
+    phi, grad = pm.pm_field(xyz, m, eps, origin, h, n, 2, pts)
+    s = orc.ParticleSet(xyz=xyz, m=m, softening=eps)
+    c = orc.cosmo()
+    for i in range(pts.shape[1]):
+        p0, g0 = orc.field_at(c, s, pts[:, i])
+        assert abs(phi[i] / p0 - 1) < 2e-3
+        assert np.linalg.norm(grad[:, i] - g0) < 1e-2 * np.linalg.norm(g0)
