@@ -47,7 +47,8 @@ FLOP_PER_INTERACTION = 20.0
 # HBM bytes per launch of the FP32 trace kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and
 # 1.0), keyed by the sha256 prefix of the kernel source they were taken with.
-MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0,
+MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0},
+                    "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 
