@@ -57,7 +57,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="nfw", choices=["nfw", "point", "box18", "box20", "batched"])
+    p.add_argument("--workload", default="nfw", choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm"])
+    p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid (nfw_pm)")
+    p.add_argument("--pm-nint", type=int, default=2, help="App. B interpolation nodes on each side (nfw_pm)")
     p.add_argument("--band", type=int, default=7168,
                    help="bundles per step of the single-field workloads (nfw, box18, box20): 7168 bundles = "
                         "1024 groups of 7 bundles, two full rounds of the 512 workgroups that the trace kernel "
@@ -101,7 +103,7 @@ def mu_stats(mu, ref):
 
 def build_workload(a):
     from paper_1110_4894_amd import workloads
-    if a.workload == "nfw":
+    if a.workload in ("nfw", "nfw_pm"):
         return workloads.nfw(), ("nfw-halo 1e5 particles (M200 1e14 Msun, c 5, z_l 0.25, z_s 0.5), 256x256 "
                                  "bundles over +-3 r_s, r_b 1e-3 arcsec, 2000 fine RK4 steps")
     if a.workload == "point":
@@ -157,6 +159,8 @@ def main():
         return
     rt.load()
     prec = rt.RT_FP64 if a.precision == "fp64" else rt.RT_FP32_KAHAN
+    if a.workload == "nfw_pm":
+        return bench_pm(a, torch, rt, workloads, GpuRun, dev)
 
     t_setup = time.time()
     w, desc = build_workload(a)
@@ -307,6 +311,98 @@ def main():
                                   "kind": "oracle", "seconds": tc,
                                   "sample": "%d bundles (%d rays) of the first timed batch, full schedules and "
                                             "particle sets, FP64" % (ws.n_bundles, 9 * ws.n_bundles)}
+    print(json.dumps(result), flush=True)
+
+
+def bench_pm(a, torch, rt, workloads, GpuRun, dev):
+    """The NFW band traced through the particle-mesh field (Sec. 3.3, App. B) instead of the
+    direct sum: build the grid once, then time bundles + trace + magnification + muPDF per band;
+    untimed, the first band is also traced with the direct sum for the mu comparison."""
+    w, desc = build_workload(a)
+    steps_w, per_step = batches(w, a)
+    f = w.fields[0]
+    s0 = f.sets[0]
+    c = rt.cosmology(w.cosmology.omega_m, w.cosmology.omega_lambda, w.cosmology.h)
+    chi_s = rt.rt_comoving_distance(c, w.z_source)
+    sched = f.schedule
+    nodes = rt.rt_make_schedule(chi_s, sched["z_lo"], sched["z_hi"], int(sched["n_fine"]), sched["q"])
+    chi_l = f.meta["chi_l"]
+    half = 1.05 * (sched["z_hi"] - chi_l)                       # grid box: the halo's r200 sphere and a margin
+    n = a.pm_n
+    h = 2 * half / (n - 1)
+    origin = (-half, -half, chi_l - half)
+    grid = rt.pm_grid(n, origin, h)
+    xyzm = torch.from_numpy(np.ascontiguousarray(np.concatenate([s0.xyz.T, s0.m[None]], 0))).to(dev)
+    pset = rt.make_particle_set(xyzm, softening=s0.softening)
+    ws_bytes = rt.rt_pm_workspace_bytes(grid)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    fields = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rt.rt_pm_build(pset, grid, fields, ws, ws_bytes)          # warm-up
+    e0.record()
+    rt.rt_pm_build(pset, grid, fields, ws, ws_bytes)
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    del ws
+    print("pm grid %d^3, h = %.2f kpc, build %.1f ms" % (n, h * 1e3, build_ms), file=sys.stderr, flush=True)
+    nb = per_step
+    thetas = [torch.from_numpy(np.ascontiguousarray(sw.fields[0].theta)).to(dev) for sw in steps_w]
+    theta = torch.empty_like(thetas[0])
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    jac = torch.empty((4, nb), dtype=torch.float64, device=dev)
+    pdf = torch.empty(200, dtype=torch.float64, device=dev)
+    mom = torch.empty(6, dtype=torch.float64, device=dev)
+    empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(len(nodes) - 1, -1, np.int32),
+                            "bundle_offset": 0, "n_bundles": nb}])
+
+    def one_step(i):
+        theta.copy_(thetas[i % len(thetas)])
+        rt.rt_build_bundles(c, empty, nb, theta, w.bundle_radius, rays)
+        flags.zero_()
+        rt.rt_trace_pm(c, w.z_source, grid, fields, a.pm_nint, nodes, 0, len(nodes) - 1, nb, rays, flags)
+        rt.rt_magnification(c, w.z_source, nb, w.bundle_radius, rays, mu, jac)
+        rt.rt_mu_histogram(nb, mu, 200, -0.1, 0.3, pdf, mom)
+
+    for i in range(a.warmup):
+        one_step(i)
+        torch.cuda.synchronize()
+        print("warmup step %d done" % i, file=sys.stderr, flush=True)
+    first = a.warmup % len(thetas)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu_first = None
+    for i in range(a.steps):
+        one_step(a.warmup + i)
+        if i == 0:
+            mu_first = mu.clone()
+        torch.cuda.synchronize()
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    ray_stages = 9.0 * nb * 4 * (len(nodes) - 1)
+    gathered = ray_stages * 4 * (2 * a.pm_nint) ** 2 * 4 * 8     # bytes of grid values read by App. B
+    result = {
+        "metric": "bundles/s through the particle-mesh field", "value": nb * a.steps / elapsed, "unit": "bundles/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc + "; field on a %d^3 particle-mesh grid (h = %.2f kpc), App. B with n_int = %d; "
+                               "one step = %d bundles" % (n, h * 1e3, a.pm_nint, nb),
+                   "name": "nfw_pm", "grid": n, "h_kpc": h * 1e3, "n_int": a.pm_nint, "rk4_steps": len(nodes) - 1},
+        "ray_stages_per_s": ray_stages * a.steps / elapsed,
+        "grid_values_read_GBps": gathered * a.steps / elapsed / 1e9,
+        "pm_build_ms": build_ms,
+    }
+    # the same band through the direct sum (FP32+Kahan), untimed
+    g = GpuRun(steps_w[first])
+    g.run(rt.RT_FP32_KAHAN)
+    md = g.mu.cpu().numpy()
+    mp = mu_first.cpu().numpy()
+    rel = np.abs(mp / md - 1)
+    result["mu_vs_direct_sum"] = {"p50": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
+                                  "max": float(rel.max()), "frac_within_3pct": float(np.mean(rel < 0.03)),
+                                  "n": int(rel.size)}
     print(json.dumps(result), flush=True)
 
 

@@ -168,11 +168,67 @@ rt_status rt_shear_histogram(int64_t n, const double* mu, const double* jac, int
 rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, rt_precision precision,
                         int64_t n, const double* points, double* phi, double* grad, hipStream_t stream);
 
+/* ---------------------------------------------------------------- particle-mesh field */
+
+/* The paper's own field representation (Sec. 3.3, App. B), for one isolated particle set:
+ * the masses are assigned to the nodes of a cubic grid by Cloud-in-Cell, and phi and its three
+ * derivatives at the nodes come from FFT convolutions with the Plummer kernels of eq. psi and
+ * eq. derivs on the grid zero-padded to (2n)^3 (the exact linear convolution of the node masses;
+ * with softening 0 a node's own mass is left out).  App. B's interpolation then gives the field
+ * anywhere inside the nodes (zero outside). */
+typedef struct rt_pm_grid {
+  int32_t n;          /* nodes per side, a power of two, 4 <= n <= 512                          */
+  double origin[3];   /* position of node (0, 0, 0), comoving Mpc; node (i, j, k) sits at
+                         origin + h (i, j, k)                                                    */
+  double h;           /* node spacing, comoving Mpc, > 0                                        */
+} rt_pm_grid;
+
+/* Workspace rt_pm_build needs: two (2n)^3 complex FP64 grids plus n twiddles, 32 (2n)^3 + 16 n bytes
+ * (4.3 GB for n = 256).  bytes: host.  Errors: RT_ERR_INVALID_ARG for a bad grid. */
+rt_status rt_pm_workspace_bytes(const rt_pm_grid* grid, size_t* bytes);
+
+/* Build the field of `set` on `grid`.  set: as for rt_trace, background must be 0 (the
+ * zero-padded convolution is the isolated-lens case of Sec. 3.3); particles whose cloud leaves
+ * the nodes lose that part of their mass.  fields: device [8][n^3] output; grid q < 4 is phi,
+ * dphi/dx, dphi/dy, dphi/dz (Mpc^0 and Mpc^-1, c = 1) and grid q + 4 its natural-spline second
+ * derivatives along z (App. B), node (i, j, k) at (i n + j) n + k.  workspace: device, at least
+ * rt_pm_workspace_bytes; contents are scratch.  The node masses are accumulated with FP64
+ * atomics, so the last bits of the result may vary between calls. */
+rt_status rt_pm_build(const rt_particle_set* set, const rt_pm_grid* grid, double* fields, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
+/* App. B interpolation of a built field at n points: n_int nodes on each side of the point
+ * (1 <= n_int <= 4, n >= 2 n_int).  points: device [3][n]; phi: device [n]; grad: device [3][n]. */
+rt_status rt_pm_eval(const rt_pm_grid* grid, const double* fields, int32_t n_int, int64_t n, const double* points,
+                     double* phi, double* grad, hipStream_t stream);
+
+/* rt_trace with the field of a built grid in place of the direct sum (one field, every step):
+ * the same RK4 in z over z_nodes (host [n_steps + 1], 0 to chi_s), the same Christoffel
+ * contraction, exit and flags.  The observer (0, 0, 0) must lie outside the grid's node box, so
+ * that the potential there is 0 as for bundles built by rt_build_bundles with no mass at step 0.
+ * rays: device [8][9 n_bundles], in and out; ray_flags: device [9 n_bundles] or NULL. */
+rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid, const double* fields,
+                      int32_t n_int, int32_t n_steps, const double* z_nodes, int32_t step_begin, int32_t step_end,
+                      int64_t n_bundles, double* rays, uint8_t* ray_flags, hipStream_t stream);
+
+/* The paper's own integrator (Sec. 3.4, eq. RKstepsize) through a built grid: classical RK4 in
+ * the affine parameter with the fixed step d_lambda = f_rk h / kz_0 per ray (h = grid.h, the
+ * L_box / n_FFT of the paper; kz_0 = the ray's kz on entry), repeated until z reaches chi_s;
+ * the step that overshoots is replaced by the linear interpolation between the previous and
+ * the current state at z = chi_s (all eight components).  A ray that has not reached chi_s
+ * after max_steps keeps its last state and is flagged 8.  f_rk > 0, max_steps >= 1; the
+ * observer must lie outside the grid as for rt_trace_pm.  rays: device [8][9 n_bundles], in and
+ * out (z on entry < chi_s); ray_flags: device [9 n_bundles] or NULL (1, 2, 4 as for rt_trace,
+ * 8 as above); ray_steps: device int32 [9 n_bundles] or NULL, steps taken per ray. */
+rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid,
+                             const double* fields, int32_t n_int, double f_rk, int32_t max_steps, int64_t n_bundles,
+                             double* rays, uint8_t* ray_flags, int32_t* ray_steps, hipStream_t stream);
+
 /* ---------------------------------------------------------------- tuning and introspection */
 
 typedef struct rt_plan_info {
   int32_t waves_per_block;    /* wavefronts in one workgroup                                 */
-  int32_t waves_per_group;    /* wavefronts that share 64 rays and split the particles      */
+  int32_t waves_per_group;    /* wavefronts that share 63 rays and split the particles      */
   int32_t tile;               /* particles per LDS tile per wavefront                        */
   int32_t rays_per_block;     /* 63 * waves_per_block / waves_per_group (7 bundles per group) */
 } rt_plan_info;

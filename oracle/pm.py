@@ -145,3 +145,92 @@ def pm_field(xyz, m, eps, origin, h, n, n_int, points):
     pts = np.asarray(points, dtype=np.float64)
     res = np.array([appb_eval(fields, y2, origin, h, n_int, pts[:, i]) for i in range(pts.shape[1])]).T
     return res[0], res[1:]
+
+
+def trace_pm(c, nodes, rays, fields, fields_y2z, origin, h, n_int, step_begin=0, step_end=2 ** 31 - 1):
+    """Classical RK4 in z over the given nodes (Sec. 3.4 with x^3 as the independent
+    variable), the field at every stage from the grid by App. B; same flags as the direct
+    oracle: 1 non-finite, 2 k^z <= 0 (both freeze the ray), 4 |phi|/a > 1e-2.
+    rays [8, R] (t, x, y, z, kt, kx, ky, kz) are updated in place; returns (rays, flags)."""
+    from . import derivs, scale_factor
+    n_steps = len(nodes) - 1
+    flags = np.zeros(rays.shape[1], dtype=np.uint8)
+    for r in range(rays.shape[1]):
+        Y = rays[[0, 1, 2, 4, 5, 6, 7], r].copy()
+        z = rays[3, r]
+        for s in range(step_begin, min(step_end, n_steps)):
+            Z0, Z1 = nodes[s], nodes[s + 1]
+            hs = Z1 - Z0
+
+            def f(Yv, zz):
+                q = appb_eval(fields, fields_y2z, origin, h, n_int, [Yv[1], Yv[2], zz])
+                return derivs(c, Yv, q[0], q[1:]), q[0]
+
+            k1, phi0 = f(Y, Z0)
+            if abs(phi0) / scale_factor(c, Y[0])[0] > 1e-2:
+                flags[r] |= 4
+            k2, _ = f(Y + 0.5 * hs * k1, Z0 + 0.5 * hs)
+            k3, _ = f(Y + 0.5 * hs * k2, Z0 + 0.5 * hs)
+            k4, _ = f(Y + hs * k3, Z1)
+            Yn = Y + hs / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            if not np.all(np.isfinite(Yn)):
+                flags[r] |= 1
+                break
+            if not Yn[6] > 0.0:
+                flags[r] |= 2
+                break
+            Y, z = Yn, Z1
+        rays[[0, 1, 2, 4, 5, 6, 7], r] = Y
+        rays[3, r] = z
+    return rays, flags
+
+
+def trace_pm_lambda(c, chi_s, rays, fields, fields_y2z, origin, h, n_int, f_rk, max_steps):
+    """The paper's own integrator (Sec. 3.4, eq. RKstepsize): classical RK4 in the affine
+    parameter with the fixed step  d_lambda = f_RK h / kz_0  (h: the grid spacing, L_box /
+    n_FFT; kz_0: the ray's dz/dlambda at the observer), repeated until z reaches chi_s; the
+    step that overshoots is replaced by the linear interpolation between the previous and
+    the current state at z = chi_s.  State (t, x, y, z, kt, kx, ky, kz), d/dlambda = (kt, kx,
+    ky, kz, -A^t, -A^x, -A^y, -A^z) with the Christoffel contraction A of the z-form.
+    Flags: 1 non-finite, 2 kz <= 0 (both freeze the ray), 4 |phi|/a > 1e-2, 8 chi_s not
+    reached within max_steps.  rays [8, R] are updated in place; returns (rays, flags, steps)."""
+    from . import accel, scale_factor
+    flags = np.zeros(rays.shape[1], dtype=np.uint8)
+    steps = np.zeros(rays.shape[1], dtype=np.int64)
+
+    def f(Y):
+        q = appb_eval(fields, fields_y2z, origin, h, n_int, Y[1:4])
+        A = accel(c, Y[0], Y[4:8], q[0], q[1:])
+        return np.concatenate([Y[4:8], -A]), q[0]
+
+    for r in range(rays.shape[1]):
+        Y = rays[:, r].copy()
+        dl = f_rk * h / Y[7]
+        done = not Y[3] < chi_s
+        for s in range(0 if done else max_steps):
+            k1, phi0 = f(Y)
+            if abs(phi0) / scale_factor(c, Y[0])[0] > 1e-2:
+                flags[r] |= 4
+            k2, _ = f(Y + 0.5 * dl * k1)
+            k3, _ = f(Y + 0.5 * dl * k2)
+            k4, _ = f(Y + dl * k3)
+            Yn = Y + dl / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            steps[r] = s + 1
+            if not np.all(np.isfinite(Yn)):
+                flags[r] |= 1
+                done = True
+                break
+            if not Yn[7] > 0.0:
+                flags[r] |= 2
+                done = True
+                break
+            if Yn[3] >= chi_s:
+                w = (chi_s - Y[3]) / (Yn[3] - Y[3])
+                Y = Y + w * (Yn - Y)
+                done = True
+                break
+            Y = Yn
+        if not done:
+            flags[r] |= 8
+        rays[:, r] = Y
+    return rays, flags, steps

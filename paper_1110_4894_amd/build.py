@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt.so")
-SOURCES = ["rt_api.hip", "rt_kernels.hip"]
-HEADERS = ["rt_internal.h", os.path.join("..", "..", "include", "rt.h")]
+SOURCES = ["rt_api.hip", "rt_kernels.hip", "rt_pm.hip"]
+HEADERS = ["rt_internal.h", "rt_geodesic.h", os.path.join("..", "..", "include", "rt.h")]
 
 # Packed FP32 instructions are switched off for every HIP source (the FP32
 # field sum is written for the scalar VALU and the transcendental unit).

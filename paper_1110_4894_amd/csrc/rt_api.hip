@@ -876,3 +876,134 @@ void rt_release_caches(void) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- particle-mesh field
+
+namespace {
+rt_status check_pm_grid(const rt_pm_grid* g) {
+  if (!g) return fail(RT_ERR_INVALID_ARG, "grid is NULL");
+  if (g->n < 4 || g->n > 512 || (g->n & (g->n - 1)) != 0)
+    return fail(RT_ERR_INVALID_ARG, "grid.n = %d must be a power of two in [4, 512]", g->n);
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(g->origin[d])) return fail(RT_ERR_NONFINITE, "grid.origin[%d] is not finite", d);
+  if (!std::isfinite(g->h)) return fail(RT_ERR_NONFINITE, "grid.h is not finite");
+  if (!(g->h > 0.0)) return fail(RT_ERR_INVALID_ARG, "grid.h must be > 0");
+  return RT_OK;
+}
+
+// The grids' potential at the observer must be 0 (bundles are built with phi_obs = 0).
+rt_status check_observer_outside(const rt_pm_grid* g) {
+  bool inside = true;
+  for (int d = 0; d < 3; ++d) {
+    const double lo = g->origin[d], hi = g->origin[d] + g->h * (g->n - 1);
+    if (!(0.0 >= lo && 0.0 <= hi)) inside = false;
+  }
+  if (inside) return fail(RT_ERR_INVALID_ARG, "the observer (0, 0, 0) lies inside the grid");
+  return RT_OK;
+}
+
+rt_status check_n_int(const rt_pm_grid* g, int32_t n_int) {
+  if (n_int < 1 || n_int > 4) return fail(RT_ERR_INVALID_ARG, "n_int = %d must be in [1, 4]", n_int);
+  if (g->n < 2 * n_int) return fail(RT_ERR_INVALID_ARG, "grid.n = %d < 2 n_int", g->n);
+  return RT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rt_status rt_pm_workspace_bytes(const rt_pm_grid* grid, size_t* bytes) {
+  rt_status st;
+  if ((st = check_pm_grid(grid)) != RT_OK) return st;
+  if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = (size_t)pm_workspace_bytes(grid->n);
+  return RT_OK;
+}
+
+rt_status rt_pm_build(const rt_particle_set* set, const rt_pm_grid* grid, double* fields, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream) {
+  rt_status st;
+  if (!set) return fail(RT_ERR_INVALID_ARG, "set is NULL");
+  if ((st = check_set(*set, 0, 0)) != RT_OK) return st;
+  if (set->background) return fail(RT_ERR_UNSUPPORTED, "rt_pm_build: background must be 0 (isolated lens)");
+  if ((st = check_pm_grid(grid)) != RT_OK) return st;
+  if (!fields || !workspace) return fail(RT_ERR_INVALID_ARG, "fields or workspace is NULL");
+  if (workspace_bytes < (size_t)pm_workspace_bytes(grid->n))
+    return fail(RT_ERR_INVALID_ARG, "workspace of %zu bytes, %lld needed", workspace_bytes,
+                (long long)pm_workspace_bytes(grid->n));
+  RT_HIP(launch_pm_build(set->xyzm, set->n, set->softening, grid->origin, grid->h, grid->n, g_over_c2(), fields,
+                         workspace, stream));
+  return RT_OK;
+}
+
+rt_status rt_pm_eval(const rt_pm_grid* grid, const double* fields, int32_t n_int, int64_t n, const double* points,
+                     double* phi, double* grad, hipStream_t stream) {
+  rt_status st;
+  if ((st = check_pm_grid(grid)) != RT_OK) return st;
+  if ((st = check_n_int(grid, n_int)) != RT_OK) return st;
+  if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return RT_OK;
+  if (!fields || !points || !phi || !grad) return fail(RT_ERR_INVALID_ARG, "fields, points, phi or grad is NULL");
+  RT_HIP(launch_pm_eval(grid->origin, grid->h, grid->n, fields, n_int, n, points, phi, grad, stream));
+  return RT_OK;
+}
+
+rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid, const double* fields,
+                      int32_t n_int, int32_t n_steps, const double* z_nodes, int32_t step_begin, int32_t step_end,
+                      int64_t n_bundles, double* rays, uint8_t* ray_flags, hipStream_t stream) {
+  rt_status st;
+  if ((st = check_cosmo(cosmo)) != RT_OK) return st;
+  if (!std::isfinite(z_source)) return fail(RT_ERR_NONFINITE, "z_source is not finite");
+  if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
+  if ((st = check_pm_grid(grid)) != RT_OK) return st;
+  if ((st = check_n_int(grid, n_int)) != RT_OK) return st;
+  if (!fields) return fail(RT_ERR_INVALID_ARG, "fields is NULL");
+  if (n_bundles < 0) return fail(RT_ERR_INVALID_ARG, "n_bundles < 0");
+  if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
+  if (step_begin < 0 || step_end < step_begin) return fail(RT_ERR_INVALID_ARG, "bad step window");
+  if (n_steps < 1 || !z_nodes) return fail(RT_ERR_SCHEDULE, "n_steps < 1 or z_nodes is NULL");
+  const double chi_s = comoving_distance(*cosmo, z_source);
+  if (z_nodes[0] != 0.0) return fail(RT_ERR_SCHEDULE, "z_nodes[0] != 0");
+  for (int s = 0; s < n_steps; ++s) {
+    if (!std::isfinite(z_nodes[s + 1])) return fail(RT_ERR_NONFINITE, "z_nodes[%d]", s + 1);
+    if (!(z_nodes[s + 1] > z_nodes[s])) return fail(RT_ERR_SCHEDULE, "z_nodes not strictly increasing at %d", s + 1);
+  }
+  if (std::fabs(z_nodes[n_steps] - chi_s) > 1e-9 * chi_s)
+    return fail(RT_ERR_SCHEDULE, "last node %.17g differs from chi_s %.17g", z_nodes[n_steps], chi_s);
+  if ((st = check_observer_outside(grid)) != RT_OK) return st;
+  const int32_t se = step_end > n_steps ? n_steps : step_end;
+  if (n_bundles == 0 || step_begin >= se) return RT_OK;
+  double* d_nodes = nullptr;
+  RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_nodes), sizeof(double) * (n_steps + 1), stream));
+  RT_HIP(hipMemcpyAsync(d_nodes, z_nodes, sizeof(double) * (n_steps + 1), hipMemcpyHostToDevice, stream));
+  RT_HIP(hipStreamSynchronize(stream));   // z_nodes is pageable host memory owned by the caller
+  RT_HIP(launch_pm_trace(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, fields, n_int, d_nodes, step_begin, se,
+                         rays, 9 * n_bundles, ray_flags, stream));
+  RT_HIP(hipFreeAsync(d_nodes, stream));
+  return RT_OK;
+}
+
+rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid,
+                             const double* fields, int32_t n_int, double f_rk, int32_t max_steps, int64_t n_bundles,
+                             double* rays, uint8_t* ray_flags, int32_t* ray_steps, hipStream_t stream) {
+  rt_status st;
+  if ((st = check_cosmo(cosmo)) != RT_OK) return st;
+  if (!std::isfinite(z_source)) return fail(RT_ERR_NONFINITE, "z_source is not finite");
+  if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
+  if ((st = check_pm_grid(grid)) != RT_OK) return st;
+  if ((st = check_n_int(grid, n_int)) != RT_OK) return st;
+  if (!fields) return fail(RT_ERR_INVALID_ARG, "fields is NULL");
+  if (!std::isfinite(f_rk)) return fail(RT_ERR_NONFINITE, "f_rk is not finite");
+  if (!(f_rk > 0.0)) return fail(RT_ERR_INVALID_ARG, "f_rk must be > 0");
+  if (max_steps < 1) return fail(RT_ERR_INVALID_ARG, "max_steps must be >= 1");
+  if (n_bundles < 0) return fail(RT_ERR_INVALID_ARG, "n_bundles < 0");
+  if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
+  if ((st = check_observer_outside(grid)) != RT_OK) return st;
+  if (n_bundles == 0) return RT_OK;
+  RT_HIP(launch_pm_trace_lambda(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, fields, n_int,
+                                comoving_distance(*cosmo, z_source), f_rk, max_steps, rays, 9 * n_bundles, ray_flags,
+                                ray_steps, stream));
+  return RT_OK;
+}
+
+}  // extern "C"
+

@@ -1,20 +1,23 @@
 // gfx950 kernels of the ray-bundle lensing path.
 //
 // Method: Killedar, Lasky, Lewis & Fluke (2011).  The hot kernel is the
-// persistent trace kernel: every wavefront owns 64 rays (one per lane) and
-// integrates them through all RK4 steps; at every stage the rays' field is the
-// direct sum over the step's particle set (Sec. 3.3, eq. psi, derivs), streamed
-// in tiles through the wavefront's own LDS slice and read back as broadcasts.
-// Several wavefronts may share the same 64 rays and split the particles
-// between them, combining their partial sums through LDS.
+// persistent trace kernel: every wavefront owns 7 whole bundles (63 rays, one
+// per lane) and integrates them through all RK4 steps; at every stage the
+// rays' field is the direct sum over the step's particle set (Sec. 3.3,
+// eq. psi, derivs), streamed in tiles through the wavefront's own LDS slice.
+// Several wavefronts may share the same rays and split the particles between
+// them, combining their partial sums through LDS in a fixed order.
 //
 // Design notes for CDNA4:
-//   * pair terms are plain VALU work (no MFMA: the sum is not a contraction);
-//     13 VALU ops per pair in FP32 plus one v_rsq on the transcendental unit;
-//   * the FP32 path works in a frame local to the wavefront: tiles are staged as
-//     particle - origin, and each lane holds its ray's offset from the origin,
-//     so FP32 differences stay well conditioned near the rays;
-//   * partial sums of each 16-particle sub-tile are added with Kahan
+//   * pair terms are plain VALU work: 13 FP32 VALU operations per pair plus one
+//     v_rsq_f32.  (A matrix-core form of the sum exists, but the FP32 frame of
+//     a bundle can be shared by at most the 4 rays of a 4x4x1 block, and that
+//     MFMA shape runs slower than the VALU loop on gfx950.)
+//   * the FP32 path works in a frame per bundle: each 64-particle tile is
+//     staged in LDS once per bundle as particle - anchor, and each lane holds
+//     its ray's small offset from its anchor, so the differences between the
+//     rays of a bundle keep full FP32 resolution;
+//   * plain FP32 partial sums over each 64-particle tile are added with Kahan
 //     compensation; FP64 is kept for the ray state and the integration;
 //   * work items (field, block of rays) are pulled from an atomic queue so that
 //     fields of very different particle counts share one launch.
@@ -24,6 +27,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "rt_geodesic.h"
 #include "rt_internal.h"
 
 namespace rt {
@@ -56,20 +60,6 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   const double r = __builtin_amdgcn_rsq(x);
   const double e = fma(-(x * r), r, 1.0);
   return fma(r * e, fma(0.375, e, 0.5), r);
-}
-
-// ---------------------------------------------------------------------------
-// Background: a(t) of eq. scalefac2 (t = lookback time) and da/dt.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void scale_factor(const DevCosmo& c, double t, double& a, double& adot) {
-  const double rate = 1.5 * c.sqrt_ol * c.H0;
-  const double u = rate * (c.t0 - t);
-  const double e = exp(u);
-  const double ie = 1.0 / e;
-  const double sh = 0.5 * (e - ie), ch = 0.5 * (e + ie);
-  a = cbrt(c.ratio * sh * sh);
-  // a^3 = ratio sh^2  =>  3 a^2 da/dt = -2 ratio sh ch rate
-  adot = -(2.0 / 3.0) * rate * c.ratio * sh * ch / (a * a);
 }
 
 // ---------------------------------------------------------------------------
@@ -113,41 +103,6 @@ __device__ void cuboid_field(const double lo[3], const double hi[3], double px, 
     gy -= s * (Z * LX + X * LZ - Y * AY);
     gz -= s * (X * LY + Y * LX - Z * AZ);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Geodesic right-hand side in z (Sec. 3.4 with x^3 as independent variable),
-// Christoffel symbols differentiated exactly from eq. expandingmetric with
-// psi = phi / a.  Y = (t, x, y, kt, kx, ky, kz).
-// ---------------------------------------------------------------------------
-struct State {
-  double t, x, y, kt, kx, ky, kz;
-};
-
-__device__ __forceinline__ State rhs(const DevCosmo& c, const State& Y, double phi, double gx, double gy, double gz,
-                                     double& a_out) {
-  double a, adot;
-  scale_factor(c, Y.t, a, adot);
-  a_out = a;
-  const double inv_a = 1.0 / a;
-  const double invE = 1.0 / (1.0 + 2.0 * phi * inv_a);
-  const double invF = 1.0 / (a * a - 2.0 * a * phi);
-  const double gk = gx * Y.kx + gy * Y.ky + gz * Y.kz;
-  const double k2 = Y.kx * Y.kx + Y.ky * Y.ky + Y.kz * Y.kz;
-  const double kt2 = Y.kt * Y.kt;
-  const double hub = adot * (a - phi);
-  const double At = (-adot * phi * inv_a * inv_a * kt2 + 2.0 * Y.kt * inv_a * gk + hub * k2) * invE;
-  const double c1 = kt2 * inv_a, c2 = 2.0 * hub * Y.kt;
-  const double Ax = (gx * c1 + c2 * Y.kx + a * (gx * k2 - 2.0 * Y.kx * gk)) * invF;
-  const double Ay = (gy * c1 + c2 * Y.ky + a * (gy * k2 - 2.0 * Y.ky * gk)) * invF;
-  const double Az = (gz * c1 + c2 * Y.kz + a * (gz * k2 - 2.0 * Y.kz * gk)) * invF;
-  const double iz = 1.0 / Y.kz;
-  return State{Y.kt * iz, Y.kx * iz, Y.ky * iz, -At * iz, -Ax * iz, -Ay * iz, -Az * iz};
-}
-
-__device__ __forceinline__ State axpy(const State& Y, double h, const State& k) {
-  return State{Y.t + h * k.t, Y.x + h * k.x, Y.y + h * k.y, Y.kt + h * k.kt, Y.kx + h * k.kx, Y.ky + h * k.ky,
-               Y.kz + h * k.kz};
 }
 
 // ---------------------------------------------------------------------------
@@ -219,40 +174,39 @@ __device__ __forceinline__ void sum_fp32(const DevSet& s, float4* tile, int q, i
   Sz = (double)s3 - (double)c3;
 }
 
-// FP64 path: tiles of the caller's FP64 particles, broadcast to every lane.
+// FP64 path: every lane needs the same particle at the same time, so the
+// caller's FP64 particles are read through the scalar unit (uniform loads from
+// the constant address space land in SGPRs and enter the FP64 VALU operations
+// as scalar operands) instead of being broadcast through LDS, whose return
+// bandwidth (32 B per lane per particle) would bound the loop.  The particles
+// are not written while a trace runs.
+typedef __attribute__((address_space(4))) const double const_double;
+
 template <int T, int WPR>
-__device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, int lane, double x, double y,
-                                         double z, double& S0, double& Sx, double& Sy, double& Sz) {
+__device__ __forceinline__ void sum_fp64(const DevSet& s, int q, double x, double y, double z, double& S0,
+                                         double& Sx, double& Sy, double& Sz) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   const int64_t n = s.n;
   const double e2 = s.eps2;
   const int64_t n_chunks = (n + T - 1) / T;
-  const double* __restrict__ px = s.p64;
+  const const_double* px = (const const_double*)s.p64;
   for (int64_t ch = q; ch < n_chunks; ch += WPR) {
     const int64_t base = ch * T;
-#pragma unroll
-    for (int k = lane; k < T; k += 64) {
-      const int64_t j = base + k;
-      tile[k] = (j < n) ? make_double4(px[j], px[n + j], px[2 * n + j], px[3 * n + j])
-                        : make_double4(1e100, 1e100, 1e100, 0.0);
-    }
-    wave_sync();
-#pragma unroll 8
-    for (int k = 0; k < T; ++k) {
-      const double4 c = tile[k];
-      const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
+    const int64_t end = base + T < n ? base + T : n;
+#pragma unroll 4
+    for (int64_t j = base; j < end; ++j) {
+      const double ex = px[j] - x, ey = px[n + j] - y, ez = px[2 * n + j] - z;
       double r2 = fma(ex, ex, e2);
       r2 = fma(ey, ey, r2);
       r2 = fma(ez, ez, r2);
       const double ri = rsqrt_f64(r2);
-      const double mr = c.w * ri;
+      const double mr = px[3 * n + j] * ri;
       a0 += mr;
       const double mr3 = mr * ri * ri;
       a1 = fma(mr3, ex, a1);
       a2 = fma(mr3, ey, a2);
       a3 = fma(mr3, ez, a3);
     }
-    wave_sync();
   }
   S0 = a0;
   Sx = a1;
@@ -263,7 +217,7 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, 
 // LDS needed by one wavefront's tiles.
 template <bool F64, int T>
 struct TileSpace {
-  static constexpr int kElems = F64 ? T : kSeg * kCopyStride;
+  static constexpr int kElems = F64 ? 1 : kSeg * kCopyStride;   // FP64 reads particles through the scalar unit
   using Elem = typename std::conditional<F64, double4, float4>::type;
 };
 
@@ -278,7 +232,7 @@ struct FieldEval {
                               double y, double z, double& phi, double& gx, double& gy, double& gz) {
     double S0, Sx, Sy, Sz;
     if constexpr (F64) {
-      sum_fp64<T, WPR>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
+      sum_fp64<T, WPR>(s, q, x, y, z, S0, Sx, Sy, Sz);
     } else {
       // positions in the set's frame (FP64), each bundle's anchor rounded to FP32
       const double X = x - s.org[0], Yv = y - s.org[1], Z = z - s.org[2];
@@ -343,14 +297,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   __shared__ double red[NG][WPR > 1 ? WPR * 4 * 64 : 1];
   __shared__ int s_item;
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform within a wavefront; saying so keeps everything derived from
+  // it (tile slices, particle chunks) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = wave / WPR, q = wave % WPR;
   const DevCosmo& cz = P.cosmo;
 
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(P.queue, 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: lets particle loads go scalar
     __syncthreads();
     if (item >= P.n_items) break;
 

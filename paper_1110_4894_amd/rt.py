@@ -56,10 +56,14 @@ class rt_trace_info(C.Structure):
                 ("grid_blocks", C.c_int32), ("n_items", C.c_int32), ("graph_reused", C.c_int32)]
 
 
+class rt_pm_grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("origin", C.c_double * 3), ("h", C.c_double)]
+
+
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
            "rt_magnification", "rt_mu_histogram", "rt_shear_histogram", "rt_field_eval", "rt_plan_count", "rt_plan_describe",
            "rt_force_plan", "rt_set_grid_limit", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
-           "rt_release_caches"]
+           "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda"]
 
 _lib = None
 
@@ -92,6 +96,11 @@ def load(path: str = LIB_PATH):
         "rt_last_trace_info": (st, [p]),
         "rt_last_error": (C.c_char_p, []),
         "rt_release_caches": (None, []),
+        "rt_pm_workspace_bytes": (st, [p, p]),
+        "rt_pm_build": (st, [p, p, p, p, C.c_size_t, p]),
+        "rt_pm_eval": (st, [p, p, i32, i64, p, p, p, p]),
+        "rt_trace_pm": (st, [p, d, p, p, i32, i32, p, i32, i32, i64, p, p, p]),
+        "rt_trace_pm_lambda": (st, [p, d, p, p, i32, d, i32, i64, p, p, p, p]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -269,3 +278,38 @@ def rt_last_error() -> str:
 
 def rt_release_caches():
     load().rt_release_caches()
+
+
+def pm_grid(n: int, origin, h: float) -> rt_pm_grid:
+    return rt_pm_grid(int(n), (C.c_double * 3)(*[float(v) for v in origin]), float(h))
+
+
+def rt_pm_workspace_bytes(grid: rt_pm_grid) -> int:
+    b = C.c_size_t(0)
+    _check(load().rt_pm_workspace_bytes(C.byref(grid), C.addressof(b)))
+    return int(b.value)
+
+
+def rt_pm_build(pset: rt_particle_set, grid: rt_pm_grid, fields, workspace, workspace_bytes: int, stream=None):
+    _check(load().rt_pm_build(C.byref(pset), C.byref(grid), _dptr(fields), _dptr(workspace), int(workspace_bytes),
+                              _stream(stream)))
+
+
+def rt_pm_eval(grid: rt_pm_grid, fields, n_int: int, n: int, points, phi, grad, stream=None):
+    _check(load().rt_pm_eval(C.byref(grid), _dptr(fields), int(n_int), int(n), _dptr(points), _dptr(phi), _dptr(grad),
+                             _stream(stream)))
+
+
+def rt_trace_pm(cosmo, z_source: float, grid: rt_pm_grid, fields, n_int: int, z_nodes, step_begin: int,
+                step_end: int, n_bundles: int, rays, ray_flags=None, stream=None):
+    nodes = np.ascontiguousarray(z_nodes, dtype=np.float64)
+    _check(load().rt_trace_pm(C.byref(cosmo), float(z_source), C.byref(grid), _dptr(fields), int(n_int),
+                              int(nodes.size - 1), nodes.ctypes.data, int(step_begin), int(step_end), int(n_bundles),
+                              _dptr(rays), _dptr(ray_flags), _stream(stream)))
+
+
+def rt_trace_pm_lambda(cosmo, z_source: float, grid: rt_pm_grid, fields, n_int: int, f_rk: float, max_steps: int,
+                       n_bundles: int, rays, ray_flags=None, ray_steps=None, stream=None):
+    _check(load().rt_trace_pm_lambda(C.byref(cosmo), float(z_source), C.byref(grid), _dptr(fields), int(n_int),
+                                     float(f_rk), int(max_steps), int(n_bundles), _dptr(rays), _dptr(ray_flags),
+                                     _dptr(ray_steps), _stream(stream)))

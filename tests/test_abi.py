@@ -126,3 +126,36 @@ def test_binding_fails_loudly_without_library(tmp_path):
             mod.load(str(tmp_path / "missing.so"))
         finally:
             mod._lib = saved
+
+
+def test_pm_argument_errors(lib):
+    """The particle-mesh entry points validate grids, n_int, sets, nodes and the observer's
+    position on the host, before any device call."""
+    c = rt.cosmology()
+    fake = 1 << 40
+    g = rt.pm_grid(32, (-1.0, -1.0, 999.0), 0.0625)
+    assert rt.rt_pm_workspace_bytes(g) == 32 * 64 ** 3 + 16 * 32
+    for bad in [rt.pm_grid(24, (0, 0, 0), 0.1), rt.pm_grid(2, (0, 0, 0), 0.1), rt.pm_grid(1024, (0, 0, 0), 0.1),
+                rt.pm_grid(32, (0, 0, 0), 0.0), rt.pm_grid(32, (0, float("inf"), 0), 0.1)]:
+        assert _status(rt.rt_pm_workspace_bytes, bad) in (-1, -3)
+    pset = rt.make_particle_set(None, softening=0.01)
+    assert _status(rt.rt_pm_build, pset, g, fake, fake, 100) == -1          # workspace too small
+    assert "workspace" in rt.rt_last_error()
+    bg = rt.make_particle_set(None, softening=0.01, background=True, lo=(0, 0, 0), hi=(1, 1, 1))
+    assert _status(rt.rt_pm_build, bg, g, fake, fake, 1 << 40) == -7       # isolated lenses only
+    assert _status(rt.rt_pm_eval, g, fake, 0, 4, fake, fake, fake) == -1
+    assert _status(rt.rt_pm_eval, g, fake, 5, 4, fake, fake, fake) == -1
+    assert _status(rt.rt_pm_eval, rt.pm_grid(4, (0, 0, 0), 0.1), fake, 3, 4, fake, fake, fake) == -1
+    chi_s = rt.rt_comoving_distance(c, 0.5)
+    nodes = rt.rt_make_schedule(chi_s, 0.0, chi_s, 10, 1.0)
+    assert _status(rt.rt_trace_pm, c, 0.5, g, fake, 2, nodes[::-1].copy(), 0, 10, 2, fake) == -4
+    assert _status(rt.rt_trace_pm, c, 0.5, g, fake, 2, nodes * 0.9, 0, 10, 2, fake) == -4
+    around = rt.pm_grid(32, (-1.0, -1.0, -1.0), 0.0625)
+    assert _status(rt.rt_trace_pm, c, 0.5, around, fake, 2, nodes, 0, 10, 2, fake) == -1
+    assert "observer" in rt.rt_last_error()
+    assert _status(rt.rt_trace_pm, c, 0.5, g, fake, 2, nodes, 5, 2, 2, fake) == -1
+    assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 2, 0.0, 100, 2, fake) == -1
+    assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 2, float("nan"), 100, 2, fake) == -3
+    assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 2, 0.5, 0, 2, fake) == -1
+    assert _status(rt.rt_trace_pm_lambda, c, 0.5, around, fake, 2, 0.5, 100, 2, fake) == -1
+    assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 9, 0.5, 100, 2, fake) == -1

@@ -1,0 +1,201 @@
+"""Parity of the particle-mesh field path (rt_pm_build, rt_pm_eval, rt_trace_pm) with
+the oracle's particle-mesh field (Sec. 3.3) and App. B interpolation.
+
+Tolerances (FP64 on both sides):
+  * grid values: within 1e-11 of the largest value of the same grid (FFT round-off);
+  * x^3 spline second derivatives, from the same grid values: 1e-12 of the largest;
+  * App. B evaluation on the same grids: 1e-12 of the grid's largest value;
+  * traced bundles through independently built grids: mu within 1e-7 relative,
+    exit positions within 1e-7 of the deflection (as for the FP64 direct sum).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc
+from oracle import pm as opm
+from paper_1110_4894_amd import rt
+from paper_1110_4894_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rt.load()
+
+
+def _cloud(n_part, centre, spread, seed, mass=1e10):
+    rng = np.random.default_rng(seed)
+    xyz = np.asarray(centre) + rng.normal(size=(n_part, 3)) * spread
+    m = rng.uniform(0.5, 1.5, n_part) * mass
+    return xyz, m
+
+
+def _build(xyz, m, eps, n, origin, h):
+    dev = torch.device("cuda")
+    xyzm = torch.from_numpy(np.ascontiguousarray(np.concatenate([xyz.T, m[None]], 0))).to(dev)
+    pset = rt.make_particle_set(xyzm, softening=eps)
+    grid = rt.pm_grid(n, origin, h)
+    nb = rt.rt_pm_workspace_bytes(grid)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    fields = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+    print("    [pm] build n=%d, %d particles, eps=%g" % (n, len(m), eps), flush=True)
+    rt.rt_pm_build(pset, grid, fields, ws, nb)
+    torch.cuda.synchronize()
+    return grid, fields, xyzm
+
+
+@pytest.mark.parametrize("n,eps,n_part", [(8, 0.0, 1), (16, 0.02, 500), (32, 0.0, 3000)])
+def test_pm_build_matches_oracle(n, eps, n_part):
+    h = 0.05
+    origin = np.array([0.3, -0.4, 100.0])
+    centre = origin + 0.5 * (n - 1) * h
+    xyz, m = _cloud(n_part, centre, 0.15 * n * h, seed=n)
+    if n_part == 1:
+        xyz = np.array([origin + h * np.array([3.3, 4.0, 2.7])])
+    grid, fields, _ = _build(xyz, m, eps, n, origin, h)
+    got = fields.cpu().numpy()
+    want = opm.isolated_field(opm.cic_deposit(xyz, m, origin, h, n), h, eps)
+    for q in range(4):
+        scale = np.abs(want[q]).max()
+        assert np.max(np.abs(got[q] - want[q])) <= 1e-11 * scale, q
+    # the x^3 splines of the GPU's own grids
+    y2 = opm.z_second_derivatives(got[:4], h)
+    for q in range(4):
+        assert np.max(np.abs(got[4 + q] - y2[q])) <= 1e-12 * np.abs(y2[q]).max() + 1e-300, q
+
+
+@pytest.mark.parametrize("n_int", [1, 2, 3, 4])
+def test_pm_eval_matches_oracle_on_the_same_grids(n_int):
+    n, h = 16, 0.05
+    origin = np.array([-0.2, 0.1, 50.0])
+    xyz, m = _cloud(400, origin + 0.5 * (n - 1) * h, 0.2, seed=7)
+    grid, fields, _ = _build(xyz, m, 0.01, n, origin, h)
+    F = fields.cpu().numpy()
+    rng = np.random.default_rng(n_int)
+    u = np.concatenate([rng.uniform(0, n - 1, (200, 3)),                       # inside
+                        rng.integers(0, n, (20, 3)).astype(float),             # on nodes
+                        np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0.2, n - 1, 7.5], [n - 1.3, 0.0, 0.1]]),
+                        rng.uniform(-1, 0, (5, 3)), rng.uniform(n - 1, n, (5, 3))])   # outside
+    pts = (origin + u * h).T.copy()
+    dev = torch.device("cuda")
+    P = torch.from_numpy(pts).to(dev)
+    phi = torch.empty(pts.shape[1], dtype=torch.float64, device=dev)
+    grad = torch.empty((3, pts.shape[1]), dtype=torch.float64, device=dev)
+    rt.rt_pm_eval(grid, fields, n_int, pts.shape[1], P, phi, grad)
+    torch.cuda.synchronize()
+    got = np.concatenate([phi.cpu().numpy()[None], grad.cpu().numpy()])
+    want = np.array([opm.appb_eval(F[:4], F[4:], origin, h, n_int, pts[:, i]) for i in range(pts.shape[1])]).T
+    for q in range(4):
+        assert np.max(np.abs(got[q] - want[q])) <= 1e-12 * np.abs(F[q]).max(), q
+    assert np.all(got[:, -10:] == 0.0)
+
+
+def test_trace_through_the_pm_field_matches_oracle():
+    """Point lens of 1e12 Msun on a 64^3 grid of 4 kpc around it; bundles at 2 and 4 theta_E
+    (21 and 42 kpc); nodes fine (2 kpc) across the grid and geometric outside."""
+    c = rt.cosmology()
+    oc = orc.cosmo()
+    w = wl.schwarzschild(n_radii=2, n_azimuth=1, x_min=2.0, x_max=4.0)
+    f = w.fields[0]
+    chi_s = rt.rt_comoving_distance(c, w.z_source)
+    chi_l = f.meta["chi_l"]
+    n, h = 64, 0.004
+    origin = np.array([-0.5 * (n - 1) * h, -0.5 * (n - 1) * h, chi_l - 0.5 * (n - 1) * h])
+    xyz = f.sets[0].xyz
+    m = f.sets[0].m
+    grid, fields, _ = _build(xyz, m, 0.0, n, origin, h)
+    nodes = rt.rt_make_schedule(chi_s, origin[2], origin[2] + (n - 1) * h, 126, 1.3)
+    dev = torch.device("cuda")
+    theta = torch.from_numpy(np.ascontiguousarray(f.theta)).to(dev)
+    nb = f.n_bundles
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(len(nodes) - 1, -1, np.int32),
+                            "bundle_offset": 0, "n_bundles": nb}])
+    rt.rt_build_bundles(c, empty, nb, theta, w.bundle_radius, rays)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    rt.rt_trace_pm(c, w.z_source, grid, fields, 2, nodes, 0, len(nodes) - 1, nb, rays, flags)
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    jac = torch.empty((4, nb), dtype=torch.float64, device=dev)
+    rt.rt_magnification(c, w.z_source, nb, w.bundle_radius, rays, mu, jac)
+    torch.cuda.synchronize()
+    g_rays, g_mu = rays.cpu().numpy(), mu.cpu().numpy()
+    assert not flags.cpu().numpy().any()
+    # oracle: its own grid, nodes and bundles
+    onodes = orc.make_schedule(orc.comoving_distance(oc, w.z_source), origin[2], origin[2] + (n - 1) * h, 126, 1.3)
+    assert np.allclose(onodes, nodes, rtol=1e-13, atol=0)      # chi_s by two different quadratures
+    ofields = opm.isolated_field(opm.cic_deposit(xyz, m, origin, h, n), h, 0.0)
+    oy2 = opm.z_second_derivatives(ofields, h)
+    ofield = orc.Field([], onodes, np.full(len(onodes) - 1, -1, np.int32), 0, nb)
+    orays = orc.build_bundles(oc, [ofield], f.theta, w.bundle_radius)
+    print("    [pm] oracle trace of %d rays over %d steps" % (orays.shape[1], len(onodes) - 1), flush=True)
+    orays, oflags = opm.trace_pm(oc, onodes, orays, ofields, oy2, origin, h, 2)
+    omu, _ = orc.magnification(orc.comoving_distance(oc, w.z_source), orays, w.bundle_radius)
+    assert not oflags.any()
+    assert np.max(np.abs(g_mu / omu - 1)) < 1e-7
+    th = np.repeat(f.theta, 9, axis=1)
+    defl = np.hypot(orays[1] - th[0] * chi_s, orays[2] - th[1] * chi_s)
+    assert np.all(np.hypot(g_rays[1] - orays[1], g_rays[2] - orays[2]) <= 1e-7 * defl + 1e-12)
+    # the lens is resolved: magnified like a point mass to within 1% (the field stops at the
+    # grid's faces, 126 kpc from the lens, and the mass is smoothed over 4 kpc cells)
+    x = f.meta["x"]
+    assert np.all(np.abs(g_mu / (1 / (1 - x ** -4)) - 1) < 0.01)
+
+
+def test_lambda_integrator_matches_oracle():
+    """The paper's affine-parameter RK4 with the step of eq. RKstepsize and the interpolated
+    last step, through the same particle-mesh field as the oracle's (z_s = 0.02, a cloud at
+    half the distance, f_RK = 0.5 and 2)."""
+    c, oc = rt.cosmology(), orc.cosmo()
+    z_s = 0.02
+    chi_s = rt.rt_comoving_distance(c, z_s)
+    chi_l = 0.5 * chi_s
+    rng = np.random.default_rng(2)
+    xyz = np.array([0.0, 0.0, chi_l]) + rng.normal(size=(200, 3)) * 0.02
+    m = np.full(200, 5e11)
+    n, h = 16, 0.02
+    origin = np.array([-0.15, -0.15, chi_l - 0.15])
+    grid, fields, _ = _build(xyz, m, 0.005, n, origin, h)
+    theta_h = np.array([[0.06 / chi_l, -0.03 / chi_l], [0.02 / chi_l, 0.05 / chi_l]])
+    radius = 0.05 * np.pi / 180 / 3600
+    nb = theta_h.shape[1]
+    dev = torch.device("cuda")
+    nodes = np.array([0.0, chi_s])
+    empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(1, -1, np.int32), "bundle_offset": 0,
+                            "n_bundles": nb}])
+    ofields = opm.isolated_field(opm.cic_deposit(xyz, m, origin, h, n), h, 0.005)
+    oy2 = opm.z_second_derivatives(ofields, h)
+    ochi = orc.comoving_distance(oc, z_s)
+    of = orc.Field([], np.array([0.0, ochi]), np.full(1, -1, np.int32), 0, nb)
+    for f_rk in (2.0, 0.5):
+        rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+        rt.rt_build_bundles(c, empty, nb, torch.from_numpy(theta_h).to(dev), radius, rays)
+        flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+        steps = torch.zeros(9 * nb, dtype=torch.int32, device=dev)
+        rt.rt_trace_pm_lambda(c, z_s, grid, fields, 2, f_rk, 10 ** 6, nb, rays, flags, steps)
+        mu = torch.empty(nb, dtype=torch.float64, device=dev)
+        rt.rt_magnification(c, z_s, nb, radius, rays, mu, None)
+        torch.cuda.synchronize()
+        print("    [pm] oracle lambda trace, f_RK = %g" % f_rk, flush=True)
+        orays = orc.build_bundles(oc, [of], theta_h, radius)
+        orays, oflags, osteps = opm.trace_pm_lambda(oc, ochi, orays, ofields, oy2, origin, h, 2, f_rk, 10 ** 6)
+        omu, _ = orc.magnification(ochi, orays, radius)
+        assert not oflags.any() and not flags.cpu().numpy().any()
+        assert np.array_equal(steps.cpu().numpy(), osteps)
+        g = rays.cpu().numpy()
+        assert np.max(np.abs(mu.cpu().numpy() / omu - 1)) < 1e-7
+        th = np.repeat(theta_h, 9, axis=1)
+        defl = np.hypot(orays[1] - th[0] * ochi, orays[2] - th[1] * ochi)
+        assert np.all(np.hypot(g[1] - orays[1], g[2] - orays[2]) <= 1e-7 * defl + 1e-12)
+        assert np.allclose(g[3], ochi, rtol=1e-13, atol=0)
+    # a ray budget that ends before the source plane is flagged 8
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    rt.rt_build_bundles(c, empty, nb, torch.from_numpy(theta_h).to(dev), radius, rays)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    rt.rt_trace_pm_lambda(c, z_s, grid, fields, 2, 2.0, 100, nb, rays, flags)
+    torch.cuda.synchronize()
+    assert np.all(flags.cpu().numpy() == 8) and np.all(rays.cpu().numpy()[3] < chi_s)

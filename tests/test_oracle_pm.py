@@ -145,3 +145,75 @@ def test_pm_field_of_a_compact_cloud_far_away_is_the_direct_sum():
         p0, g0 = orc.field_at(c, s, pts[:, i])
         assert abs(phi[i] / p0 - 1) < 2e-3
         assert np.linalg.norm(grad[:, i] - g0) < 1e-2 * np.linalg.norm(g0)
+
+
+def _empty_field_rays(c, theta, radius, nodes):
+    f = orc.Field([], nodes, np.full(len(nodes) - 1, -1, np.int32), 0, theta.shape[1])
+    return orc.build_bundles(c, [f], theta, radius)
+
+
+def test_lambda_integrator_straight_rays_without_mass():
+    """Sec. 3.4 integrator with no field: x/z stays constant along every ray, so the
+    overshooting step's linear interpolation lands exactly on theta chi_s and mu = 1."""
+    c = orc.cosmo()
+    chi_s = orc.comoving_distance(c, 0.02)
+    theta = np.array([[1e-3, -2e-3], [4e-4, 7e-4]])
+    radius = 1e-3 * math.pi / 180 / 3600
+    rays = _empty_field_rays(c, theta, radius, np.array([0.0, chi_s]))
+    n, h = 8, 0.5
+    F = np.zeros((4, n, n, n))
+    out, flags, steps = pm.trace_pm_lambda(c, chi_s, rays.copy(), F, F, np.array([-2.0, -2.0, 10.0]), h, 2, 1.0,
+                                           10 ** 6)
+    assert not flags.any()
+    assert np.all(np.abs(out[3] / chi_s - 1) < 1e-13)
+    th = np.repeat(theta, 9, axis=1)
+    ang = np.tile(np.concatenate([[0.0], np.arange(8) * math.pi / 4]), 2)
+    ring = np.tile(np.concatenate([[0.0], np.ones(8)]), 2) * radius
+    tx, ty = th[0] + ring * np.cos(ang), th[1] + ring * np.sin(ang)
+    assert np.allclose(out[1], tx * chi_s, rtol=1e-11, atol=0)
+    assert np.allclose(out[2], ty * chi_s, rtol=1e-11, atol=0)
+    mu, _ = orc.magnification(chi_s, out, radius)
+    assert np.all(np.abs(mu - 1) < 1e-6)
+    # dz/dlambda grows towards the source (k scales with 1 + z), so a little fewer than
+    # chi_s / (f_RK h) steps
+    assert np.all((steps > chi_s / 0.5 / (1 + 0.03)) & (steps <= chi_s / 0.5 + 1))
+    # null invariant E kt^2 - F |k|^2 with phi = 0 (E = 1, F = a^2)
+    a = np.array([orc.scale_factor(c, t)[0] for t in out[0]])
+    # (RK4 truncation of 0.5 Mpc steps and the interpolated last step: ~1e-8)
+    assert np.max(np.abs(out[4] ** 2 - a * a * (out[5] ** 2 + out[6] ** 2 + out[7] ** 2)) / out[4] ** 2) < 5e-8
+
+
+def test_lambda_integrator_converges_to_the_z_integrator():
+    """Through the same particle-mesh field, the lambda-stepping integrator approaches the
+    z-stepping one as f_RK shrinks.  The field stops at the grid's faces, and a fixed step
+    straddles a face wherever it falls, so the convergence is first order with a constant that
+    depends on that phase: only the overall decrease is pinned (Sec. 4.1 finds f_RK = 0.5
+    sufficient)."""
+    c = orc.cosmo()
+    z_s = 0.02
+    chi_s = orc.comoving_distance(c, z_s)
+    chi_l = 0.5 * chi_s
+    rng = np.random.default_rng(2)
+    xyz = np.array([0.0, 0.0, chi_l]) + rng.normal(size=(200, 3)) * 0.02
+    m = np.full(200, 5e11)
+    n, h = 16, 0.02
+    origin = np.array([-0.15, -0.15, chi_l - 0.15])
+    F = pm.isolated_field(pm.cic_deposit(xyz, m, origin, h, n), h, 0.005)
+    F2 = pm.z_second_derivatives(F, h)
+    theta = np.array([[0.06 / chi_l], [0.02 / chi_l]])
+    radius = 0.05 * math.pi / 180 / 3600
+    nodes = orc.make_schedule(chi_s, origin[2], origin[2] + (n - 1) * h, 300, 1.02)
+    ref, fl = pm.trace_pm(c, nodes, _empty_field_rays(c, theta, radius, nodes), F, F2, origin, h, 2)
+    assert not fl.any()
+    mu_ref, _ = orc.magnification(chi_s, ref, radius)
+    defl = np.hypot(ref[1] - theta[0] * chi_s, ref[2] - theta[1] * chi_s)
+    assert defl.min() > 1e-5                          # the rays are deflected
+    errs = []
+    for f_rk in (8.0, 0.5):
+        out, flags, _ = pm.trace_pm_lambda(c, chi_s, _empty_field_rays(c, theta, radius, nodes), F, F2, origin, h,
+                                           2, f_rk, 10 ** 6)
+        assert not flags.any()
+        mu, _ = orc.magnification(chi_s, out, radius)
+        errs.append(max(np.max(np.hypot(out[1] - ref[1], out[2] - ref[2]) / defl), abs(mu[0] / mu_ref[0] - 1)))
+    assert errs[1] < 1e-3
+    assert errs[0] > 20 * errs[1]
