@@ -46,7 +46,8 @@ PEAK_FP64 = 78.6       # TFLOP/s, MI355X FP64 vector (published)
 FLOP_PER_INTERACTION = 20.0
 # HBM bytes per launch of the FP32 trace kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and
-# 1.0), keyed by the sha256 prefix of the kernel source they were taken with.
+# 1.0), keyed by the sha256 prefix of the kernel sources they were taken with
+# (kernel_source_sha; the first two entries hashed rt_kernels.hip alone).
 MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0},
                     "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
@@ -60,6 +61,9 @@ def parse():
     p.add_argument("--workload", default="nfw", choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm"])
     p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid (nfw_pm)")
     p.add_argument("--pm-nint", type=int, default=2, help="App. B interpolation nodes on each side (nfw_pm)")
+    p.add_argument("--pm-frk", type=float, default=0.0,
+                   help="nfw_pm: > 0 integrates in the affine parameter with the step f_RK h / kz_0 (eq. RKstepsize) "
+                        "instead of the z nodes")
     p.add_argument("--band", type=int, default=7168,
                    help="bundles per step of the single-field workloads (nfw, box18, box20): 7168 bundles = "
                         "1024 groups of 7 bundles, two full rounds of the 512 workgroups that the trace kernel "
@@ -78,11 +82,18 @@ def parse():
     return p.parse_args()
 
 
+def kernel_source_sha() -> str:
+    """sha256 prefix of the sources the trace kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in ("rt_kernels.hip", "rt_geodesic.h", "rt_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1110_4894_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_bytes(a):
     """Measured HBM bytes per trace launch, or None when the kernel source has changed
     since the counters were taken or the launch differs from the profiled one."""
-    src = os.path.join(ROOT, "paper_1110_4894_amd", "csrc", "rt_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_sha()
     m = MEASURED_TRAFFIC.get(sha)
     if m is None or a.workload != "nfw" or a.band != 7168 or a.precision != "fp32k":
         return None
@@ -357,12 +368,16 @@ def bench_pm(a, torch, rt, workloads, GpuRun, dev):
     mom = torch.empty(6, dtype=torch.float64, device=dev)
     empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(len(nodes) - 1, -1, np.int32),
                             "bundle_offset": 0, "n_bundles": nb}])
+    steps = torch.zeros(9 * nb, dtype=torch.int32, device=dev)
 
     def one_step(i):
         theta.copy_(thetas[i % len(thetas)])
         rt.rt_build_bundles(c, empty, nb, theta, w.bundle_radius, rays)
         flags.zero_()
-        rt.rt_trace_pm(c, w.z_source, grid, fields, a.pm_nint, nodes, 0, len(nodes) - 1, nb, rays, flags)
+        if a.pm_frk > 0:
+            rt.rt_trace_pm_lambda(c, w.z_source, grid, fields, a.pm_nint, a.pm_frk, 1 << 30, nb, rays, flags, steps)
+        else:
+            rt.rt_trace_pm(c, w.z_source, grid, fields, a.pm_nint, nodes, 0, len(nodes) - 1, nb, rays, flags)
         rt.rt_magnification(c, w.z_source, nb, w.bundle_radius, rays, mu, jac)
         rt.rt_mu_histogram(nb, mu, 200, -0.1, 0.3, pdf, mom)
 
@@ -381,15 +396,19 @@ def bench_pm(a, torch, rt, workloads, GpuRun, dev):
         torch.cuda.synchronize()
         print("step %d done" % i, file=sys.stderr, flush=True)
     elapsed = time.perf_counter() - t0
-    ray_stages = 9.0 * nb * 4 * (len(nodes) - 1)
+    n_rk = float(steps.double().mean()) if a.pm_frk > 0 else float(len(nodes) - 1)
+    ray_stages = 9.0 * nb * 4 * n_rk
     gathered = ray_stages * 4 * (2 * a.pm_nint) ** 2 * 4 * 8     # bytes of grid values read by App. B
     result = {
         "metric": "bundles/s through the particle-mesh field", "value": nb * a.steps / elapsed, "unit": "bundles/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": desc + "; field on a %d^3 particle-mesh grid (h = %.2f kpc), App. B with n_int = %d; "
-                               "one step = %d bundles" % (n, h * 1e3, a.pm_nint, nb),
-                   "name": "nfw_pm", "grid": n, "h_kpc": h * 1e3, "n_int": a.pm_nint, "rk4_steps": len(nodes) - 1},
+        "config": {"workload": desc + "; field on a %d^3 particle-mesh grid (h = %.2f kpc), App. B with n_int = %d, %s; "
+                               "one step = %d bundles" % (n, h * 1e3, a.pm_nint,
+                                                          ("RK4 in the affine parameter, f_RK = %g" % a.pm_frk)
+                                                          if a.pm_frk > 0 else "RK4 over the z nodes", nb),
+                   "name": "nfw_pm", "grid": n, "h_kpc": h * 1e3, "n_int": a.pm_nint, "f_rk": a.pm_frk,
+                   "rk4_steps_per_ray": n_rk},
         "ray_stages_per_s": ray_stages * a.steps / elapsed,
         "grid_values_read_GBps": gathered * a.steps / elapsed / 1e9,
         "pm_build_ms": build_ms,

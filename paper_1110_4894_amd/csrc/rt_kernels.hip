@@ -174,39 +174,40 @@ __device__ __forceinline__ void sum_fp32(const DevSet& s, float4* tile, int q, i
   Sz = (double)s3 - (double)c3;
 }
 
-// FP64 path: every lane needs the same particle at the same time, so the
-// caller's FP64 particles are read through the scalar unit (uniform loads from
-// the constant address space land in SGPRs and enter the FP64 VALU operations
-// as scalar operands) instead of being broadcast through LDS, whose return
-// bandwidth (32 B per lane per particle) would bound the loop.  The particles
-// are not written while a trace runs.
-typedef __attribute__((address_space(4))) const double const_double;
-
+// FP64 path: tiles of the caller's FP64 particles, broadcast to every lane.
 template <int T, int WPR>
-__device__ __forceinline__ void sum_fp64(const DevSet& s, int q, double x, double y, double z, double& S0,
-                                         double& Sx, double& Sy, double& Sz) {
+__device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, int lane, double x, double y,
+                                         double z, double& S0, double& Sx, double& Sy, double& Sz) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   const int64_t n = s.n;
   const double e2 = s.eps2;
   const int64_t n_chunks = (n + T - 1) / T;
-  const const_double* px = (const const_double*)s.p64;
+  const double* __restrict__ px = s.p64;
   for (int64_t ch = q; ch < n_chunks; ch += WPR) {
     const int64_t base = ch * T;
-    const int64_t end = base + T < n ? base + T : n;
-#pragma unroll 4
-    for (int64_t j = base; j < end; ++j) {
-      const double ex = px[j] - x, ey = px[n + j] - y, ez = px[2 * n + j] - z;
+#pragma unroll
+    for (int k = lane; k < T; k += 64) {
+      const int64_t j = base + k;
+      tile[k] = (j < n) ? make_double4(px[j], px[n + j], px[2 * n + j], px[3 * n + j])
+                        : make_double4(1e100, 1e100, 1e100, 0.0);
+    }
+    wave_sync();
+#pragma unroll 8
+    for (int k = 0; k < T; ++k) {
+      const double4 c = tile[k];
+      const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
       double r2 = fma(ex, ex, e2);
       r2 = fma(ey, ey, r2);
       r2 = fma(ez, ez, r2);
       const double ri = rsqrt_f64(r2);
-      const double mr = px[3 * n + j] * ri;
+      const double mr = c.w * ri;
       a0 += mr;
       const double mr3 = mr * ri * ri;
       a1 = fma(mr3, ex, a1);
       a2 = fma(mr3, ey, a2);
       a3 = fma(mr3, ez, a3);
     }
+    wave_sync();
   }
   S0 = a0;
   Sx = a1;
@@ -217,7 +218,7 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, int q, double x, doubl
 // LDS needed by one wavefront's tiles.
 template <bool F64, int T>
 struct TileSpace {
-  static constexpr int kElems = F64 ? 1 : kSeg * kCopyStride;   // FP64 reads particles through the scalar unit
+  static constexpr int kElems = F64 ? T : kSeg * kCopyStride;
   using Elem = typename std::conditional<F64, double4, float4>::type;
 };
 
@@ -232,7 +233,7 @@ struct FieldEval {
                               double y, double z, double& phi, double& gx, double& gy, double& gz) {
     double S0, Sx, Sy, Sz;
     if constexpr (F64) {
-      sum_fp64<T, WPR>(s, q, x, y, z, S0, Sx, Sy, Sz);
+      sum_fp64<T, WPR>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
     } else {
       // positions in the set's frame (FP64), each bundle's anchor rounded to FP32
       const double X = x - s.org[0], Yv = y - s.org[1], Z = z - s.org[2];
@@ -297,16 +298,14 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   __shared__ double red[NG][WPR > 1 ? WPR * 4 * 64 : 1];
   __shared__ int s_item;
 
-  // the wavefront index is uniform within a wavefront; saying so keeps everything derived from
-  // it (tile slices, particle chunks) in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = wave / WPR, q = wave % WPR;
   const DevCosmo& cz = P.cosmo;
 
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(P.queue, 1);
     __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: lets particle loads go scalar
+    const int item = s_item;
     __syncthreads();
     if (item >= P.n_items) break;
 
