@@ -83,9 +83,9 @@ def parse():
 
 
 def kernel_source_sha() -> str:
-    """sha256 prefix of the sources the trace kernel is compiled from."""
+    """sha256 prefix of the trace kernel's code (its kernel file and the shared geodesic header)."""
     h = hashlib.sha256()
-    for f in ("rt_kernels.hip", "rt_geodesic.h", "rt_internal.h"):
+    for f in ("rt_kernels.hip", "rt_geodesic.h"):
         h.update(open(os.path.join(ROOT, "paper_1110_4894_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -419,9 +419,14 @@ def bench_pm(a, torch, rt, workloads, GpuRun, dev):
     md = g.mu.cpu().numpy()
     mp = mu_first.cpu().numpy()
     rel = np.abs(mp / md - 1)
+    th = steps_w[first].fields[0].theta
+    r_rs = np.hypot(th[0], th[1]) * f.meta["d_d"] / f.meta["rs_phys"]      # impact parameter / r_s
+    bad = rel >= 0.03
     result["mu_vs_direct_sum"] = {"p50": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
-                                  "max": float(rel.max()), "frac_within_3pct": float(np.mean(rel < 0.03)),
-                                  "n": int(rel.size)}
+                                  "max": float(rel.max()), "frac_within_3pct": float(np.mean(~bad)),
+                                  "n": int(rel.size), "impact_over_rs_p50_all": float(np.median(r_rs)),
+                                  "impact_over_rs_max_beyond_3pct": float(r_rs[bad].max()) if bad.any() else None,
+                                  "impact_over_rs_min_within_3pct": float(r_rs[~bad].min()) if (~bad).any() else None}
     print(json.dumps(result), flush=True)
 
 

@@ -170,26 +170,34 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
 
 /* ---------------------------------------------------------------- particle-mesh field */
 
-/* The paper's own field representation (Sec. 3.3, App. B), for one isolated particle set:
- * the masses are assigned to the nodes of a cubic grid by Cloud-in-Cell, and phi and its three
- * derivatives at the nodes come from FFT convolutions with the Plummer kernels of eq. psi and
- * eq. derivs on the grid zero-padded to (2n)^3 (the exact linear convolution of the node masses;
- * with softening 0 a node's own mass is left out).  App. B's interpolation then gives the field
- * anywhere inside the nodes (zero outside). */
+/* The paper's own field representation (Sec. 3.3, App. B) for one particle set: the masses are
+ * assigned to the nodes of a cubic grid by Cloud-in-Cell, and phi and its three derivatives at
+ * the nodes come from FFTs.
+ *   Isolated grid (periodic = 0): convolution with the Plummer kernels of eq. psi and eq. derivs on
+ *   the grid zero-padded to (2n)^3 (the exact linear convolution of the node masses; with
+ *   softening 0 a node's own mass is left out); App. B's interpolation gives the field anywhere
+ *   inside the nodes, zero outside.
+ *   Periodic grid (periodic = 1): the n^3 nodes tile a box of side n h and the deposit wraps;
+ *   phi_k = -4 pi (G/c^2) rho_k / k^2 (continuum Green's function, k = 0 removed, so the box's mean
+ *   density is subtracted; no softening beyond the mesh) and dphi/dx_j = i k_j phi_k; the x^3
+ *   spline is periodic and App. B's windows wrap, so every point of space has a field. */
 typedef struct rt_pm_grid {
   int32_t n;          /* nodes per side, a power of two, 4 <= n <= 512                          */
   double origin[3];   /* position of node (0, 0, 0), comoving Mpc; node (i, j, k) sits at
                          origin + h (i, j, k)                                                    */
   double h;           /* node spacing, comoving Mpc, > 0                                        */
+  int32_t periodic;   /* 0: isolated lens, 1: periodic box                                      */
 } rt_pm_grid;
 
-/* Workspace rt_pm_build needs: two (2n)^3 complex FP64 grids plus n twiddles, 32 (2n)^3 + 16 n bytes
- * (4.3 GB for n = 256).  bytes: host.  Errors: RT_ERR_INVALID_ARG for a bad grid. */
+/* Workspace rt_pm_build needs: two M^3 complex FP64 grids plus M/2 twiddles, 32 M^3 + 8 M bytes,
+ * with M = 2n for an isolated grid (4.3 GB for n = 256) and M = n for a periodic one.
+ * bytes: host.  Errors: RT_ERR_INVALID_ARG for a bad grid. */
 rt_status rt_pm_workspace_bytes(const rt_pm_grid* grid, size_t* bytes);
 
-/* Build the field of `set` on `grid`.  set: as for rt_trace, background must be 0 (the
- * zero-padded convolution is the isolated-lens case of Sec. 3.3); particles whose cloud leaves
- * the nodes lose that part of their mass.  fields: device [8][n^3] output; grid q < 4 is phi,
+/* Build the field of `set` on `grid`.  set: as for rt_trace; on an isolated grid background
+ * must be 0 and particles whose cloud leaves the nodes lose that part of their mass; on a
+ * periodic grid the background flag is ignored (the mean is removed by construction) and every
+ * particle is wrapped into the box.  fields: device [8][n^3] output; grid q < 4 is phi,
  * dphi/dx, dphi/dy, dphi/dz (Mpc^0 and Mpc^-1, c = 1) and grid q + 4 its natural-spline second
  * derivatives along z (App. B), node (i, j, k) at (i n + j) n + k.  workspace: device, at least
  * rt_pm_workspace_bytes; contents are scratch.  The node masses are accumulated with FP64
@@ -202,7 +210,8 @@ rt_status rt_pm_build(const rt_particle_set* set, const rt_pm_grid* grid, double
 rt_status rt_pm_eval(const rt_pm_grid* grid, const double* fields, int32_t n_int, int64_t n, const double* points,
                      double* phi, double* grad, hipStream_t stream);
 
-/* rt_trace with the field of a built grid in place of the direct sum (one field, every step):
+/* rt_trace with the field of a built isolated grid in place of the direct sum (one field, every
+ * step; RT_ERR_UNSUPPORTED for a periodic grid):
  * the same RK4 in z over z_nodes (host [n_steps + 1], 0 to chi_s), the same Christoffel
  * contraction, exit and flags.  The observer (0, 0, 0) must lie outside the grid's node box, so
  * that the potential there is 0 as for bundles built by rt_build_bundles with no mass at step 0.

@@ -22,6 +22,13 @@ What is computed (isolated lenses, the zero-padded case of Sec. 3.3):
    one local natural spline along x^2.  The local windows hold n_int nodes on
    each side of the point, shifted inwards at the grid's edges; outside the
    node range the field is zero.
+
+Periodic boxes (the cosmological case of Sec. 3.3): the n^3 nodes tile a box of
+side L = n h; the deposit wraps; the mean node mass is subtracted; the
+potential solves Poisson's equation with the continuum Green's function,
+phi_k = -4 pi (G/c^2) rho_k / k^2 (k = 0 removed), and dphi/dx_j has the
+transform i k_j phi_k; the x^3 spline is the periodic cubic spline; App. B's
+windows wrap around instead of shifting, and every point of space is inside.
 """
 from __future__ import annotations
 
@@ -134,6 +141,78 @@ def appb_eval(fields: np.ndarray, fields_y2z: np.ndarray, origin, h: float, n_in
         # steps 2-3: local splines along x^1, one per x^2 node of the window
         w = np.array([_local_spline(wx, v[:, b], u[0], h) for b in range(2 * n_int)])
         # steps 4-5: one local spline along x^2
+        out[q] = _local_spline(wy, w, u[1], h)
+    return out
+
+
+def cic_deposit_periodic(xyz: np.ndarray, m: np.ndarray, origin, h: float, n: int) -> np.ndarray:
+    """Cloud-in-Cell on the n^3 nodes of a periodic box of side n h (Sec. 3.3)."""
+    u = (np.asarray(xyz, dtype=np.float64) - np.asarray(origin, dtype=np.float64)) / h
+    i0 = np.floor(u).astype(np.int64)
+    f = u - i0
+    grid = np.zeros((n, n, n))
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                w = ((f[:, 0] if a else 1 - f[:, 0]) * (f[:, 1] if b else 1 - f[:, 1]) *
+                     (f[:, 2] if c else 1 - f[:, 2]))
+                idx = np.mod(i0 + np.array([a, b, c]), n)
+                np.add.at(grid, (idx[:, 0], idx[:, 1], idx[:, 2]), m * w)
+    return grid
+
+
+def periodic_field(mass: np.ndarray, h: float) -> np.ndarray:
+    """[4, n, n, n]: phi and its gradient at the nodes of a periodic box: the density
+    contrast (mean node mass removed) through the continuum Green's function of
+    Poisson's equation, derivatives as i k_j (Sec. 3.3, eq. psi, derivs)."""
+    n = mass.shape[0]
+    G = G_over_c2()
+    rho = (mass - mass.mean()) / h ** 3
+    rk = np.fft.fftn(rho)
+    k = 2 * np.pi * np.fft.fftfreq(n, d=h)
+    kx, ky, kz = np.meshgrid(k, k, k, indexing="ij")
+    k2 = kx * kx + ky * ky + kz * kz
+    with np.errstate(divide="ignore", invalid="ignore"):
+        phik = np.where(k2 > 0, -4 * np.pi * G * rk / k2, 0.0)
+    out = np.empty((4, n, n, n))
+    out[0] = np.real(np.fft.ifftn(phik))
+    for q, kq in enumerate((kx, ky, kz)):
+        out[1 + q] = np.real(np.fft.ifftn(1j * kq * phik))
+    return out
+
+
+def spline_y2_periodic(y: np.ndarray, h: float) -> np.ndarray:
+    """Periodic cubic-spline second derivatives along the last axis: the circulant
+    system y2[k-1] + 4 y2[k] + y2[k+1] = 6 (y[k+1] - 2 y[k] + y[k-1]) / h^2, indices mod n."""
+    from scipy.linalg import solve_circulant
+    m = y.shape[-1]
+    col = np.zeros(m)
+    col[0], col[1], col[-1] = 4.0, 1.0, 1.0
+    rhs = 6.0 * (np.roll(y, -1, axis=-1) - 2.0 * y + np.roll(y, 1, axis=-1)) / (h * h)
+    flat = rhs.reshape(-1, m)
+    sol = np.array([solve_circulant(col, r) for r in flat])
+    return sol.reshape(y.shape)
+
+
+def appb_eval_periodic(fields: np.ndarray, fields_y2z: np.ndarray, origin, h: float, n_int: int, p) -> np.ndarray:
+    """App. B on a periodic grid: the point is wrapped into the box, the x^3 segment and the
+    x^1, x^2 windows (n_int nodes on each side) are taken modulo n."""
+    n = fields.shape[1]
+    u = np.mod((np.asarray(p, dtype=np.float64) - np.asarray(origin, dtype=np.float64)) / h, n)
+    fl = np.floor(u).astype(np.int64)
+    wx = fl[0] - n_int + 1 + np.arange(2 * n_int)
+    wy = fl[1] - n_int + 1 + np.arange(2 * n_int)
+    kz = fl[2]
+    Az = (kz + 1) - u[2]
+    out = np.empty(4)
+    for q in range(4):
+        F, F2 = fields[q], fields_y2z[q]
+        v = np.empty((2 * n_int, 2 * n_int))
+        for a, i in enumerate(wx % n):
+            for b, j in enumerate(wy % n):
+                v[a, b] = spline_eval(F[i, j, kz % n], F[i, j, (kz + 1) % n], F2[i, j, kz % n],
+                                      F2[i, j, (kz + 1) % n], Az, h)
+        w = np.array([_local_spline(wx, v[:, b], u[0], h) for b in range(2 * n_int)])
         out[q] = _local_spline(wy, w, u[1], h)
     return out
 

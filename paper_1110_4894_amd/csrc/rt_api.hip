@@ -888,11 +888,14 @@ rt_status check_pm_grid(const rt_pm_grid* g) {
     if (!std::isfinite(g->origin[d])) return fail(RT_ERR_NONFINITE, "grid.origin[%d] is not finite", d);
   if (!std::isfinite(g->h)) return fail(RT_ERR_NONFINITE, "grid.h is not finite");
   if (!(g->h > 0.0)) return fail(RT_ERR_INVALID_ARG, "grid.h must be > 0");
+  if (g->periodic != 0 && g->periodic != 1) return fail(RT_ERR_INVALID_ARG, "grid.periodic must be 0 or 1");
   return RT_OK;
 }
 
-// The grids' potential at the observer must be 0 (bundles are built with phi_obs = 0).
+// The grids' potential at the observer must be 0 (bundles are built with phi_obs = 0),
+// so traces take isolated grids that leave the observer outside their nodes.
 rt_status check_observer_outside(const rt_pm_grid* g) {
+  if (g->periodic) return fail(RT_ERR_UNSUPPORTED, "traces through a periodic grid are not supported");
   bool inside = true;
   for (int d = 0; d < 3; ++d) {
     const double lo = g->origin[d], hi = g->origin[d] + g->h * (g->n - 1);
@@ -915,7 +918,7 @@ rt_status rt_pm_workspace_bytes(const rt_pm_grid* grid, size_t* bytes) {
   rt_status st;
   if ((st = check_pm_grid(grid)) != RT_OK) return st;
   if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
-  *bytes = (size_t)pm_workspace_bytes(grid->n);
+  *bytes = (size_t)pm_workspace_bytes(grid->n, grid->periodic);
   return RT_OK;
 }
 
@@ -924,14 +927,15 @@ rt_status rt_pm_build(const rt_particle_set* set, const rt_pm_grid* grid, double
   rt_status st;
   if (!set) return fail(RT_ERR_INVALID_ARG, "set is NULL");
   if ((st = check_set(*set, 0, 0)) != RT_OK) return st;
-  if (set->background) return fail(RT_ERR_UNSUPPORTED, "rt_pm_build: background must be 0 (isolated lens)");
   if ((st = check_pm_grid(grid)) != RT_OK) return st;
+  if (set->background && !grid->periodic)
+    return fail(RT_ERR_UNSUPPORTED, "rt_pm_build: an isolated grid needs background = 0");
   if (!fields || !workspace) return fail(RT_ERR_INVALID_ARG, "fields or workspace is NULL");
-  if (workspace_bytes < (size_t)pm_workspace_bytes(grid->n))
-    return fail(RT_ERR_INVALID_ARG, "workspace of %zu bytes, %lld needed", workspace_bytes,
-                (long long)pm_workspace_bytes(grid->n));
-  RT_HIP(launch_pm_build(set->xyzm, set->n, set->softening, grid->origin, grid->h, grid->n, g_over_c2(), fields,
-                         workspace, stream));
+  const int64_t need = pm_workspace_bytes(grid->n, grid->periodic);
+  if (workspace_bytes < (size_t)need)
+    return fail(RT_ERR_INVALID_ARG, "workspace of %zu bytes, %lld needed", workspace_bytes, (long long)need);
+  RT_HIP(launch_pm_build(set->xyzm, set->n, set->softening, grid->origin, grid->h, grid->n, grid->periodic,
+                         g_over_c2(), fields, workspace, stream));
   return RT_OK;
 }
 
@@ -943,7 +947,7 @@ rt_status rt_pm_eval(const rt_pm_grid* grid, const double* fields, int32_t n_int
   if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");
   if (n == 0) return RT_OK;
   if (!fields || !points || !phi || !grad) return fail(RT_ERR_INVALID_ARG, "fields, points, phi or grad is NULL");
-  RT_HIP(launch_pm_eval(grid->origin, grid->h, grid->n, fields, n_int, n, points, phi, grad, stream));
+  RT_HIP(launch_pm_eval(grid->origin, grid->h, grid->n, grid->periodic, fields, n_int, n, points, phi, grad, stream));
   return RT_OK;
 }
 
@@ -976,8 +980,8 @@ rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, const rt_pm_gr
   RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_nodes), sizeof(double) * (n_steps + 1), stream));
   RT_HIP(hipMemcpyAsync(d_nodes, z_nodes, sizeof(double) * (n_steps + 1), hipMemcpyHostToDevice, stream));
   RT_HIP(hipStreamSynchronize(stream));   // z_nodes is pageable host memory owned by the caller
-  RT_HIP(launch_pm_trace(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, fields, n_int, d_nodes, step_begin, se,
-                         rays, 9 * n_bundles, ray_flags, stream));
+  RT_HIP(launch_pm_trace(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, grid->periodic, fields, n_int, d_nodes,
+                         step_begin, se, rays, 9 * n_bundles, ray_flags, stream));
   RT_HIP(hipFreeAsync(d_nodes, stream));
   return RT_OK;
 }
@@ -999,7 +1003,7 @@ rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const r
   if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
   if ((st = check_observer_outside(grid)) != RT_OK) return st;
   if (n_bundles == 0) return RT_OK;
-  RT_HIP(launch_pm_trace_lambda(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, fields, n_int,
+  RT_HIP(launch_pm_trace_lambda(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, grid->periodic, fields, n_int,
                                 comoving_distance(*cosmo, z_source), f_rk, max_steps, rays, 9 * n_bundles, ray_flags,
                                 ray_steps, stream));
   return RT_OK;

@@ -13,6 +13,9 @@
 //     dphi/dx = (G/c^2) sum M d_x (d^2 + eps^2)^(-3/2) at every node;
 //   * natural cubic-spline second derivatives of each of the four grids along
 //     the line of sight x^3 (computed once per grid, App. B).
+// Periodic boxes: the deposit wraps, the node masses' transform is multiplied
+// by the continuum Green's function of Poisson's equation (and i k_j for the
+// derivatives), and the x^3 spline is the periodic one.
 // Evaluation at a point (App. B, n_int nodes on each side): (2 n_int)^2 spline
 // evaluations along x^3, 2 n_int local natural splines along x^1, one local
 // natural spline along x^2; zero outside the node range.
@@ -49,7 +52,7 @@ __global__ void pm_twiddle_kernel(double2* tw, int M) {
 }
 
 __global__ void pm_cic_kernel(const double* __restrict__ xyzm, int64_t np, double ox, double oy, double oz, double h,
-                              int n, int M, double2* buf) {
+                              int n, int M, int periodic, double2* buf) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
   const double u[3] = {(xyzm[p] - ox) / h, (xyzm[np + p] - oy) / h, (xyzm[2 * np + p] - oz) / h};
@@ -64,8 +67,14 @@ __global__ void pm_cic_kernel(const double* __restrict__ xyzm, int64_t np, doubl
 #pragma unroll
   for (int corner = 0; corner < 8; ++corner) {
     const int a = corner >> 2, b = (corner >> 1) & 1, c = corner & 1;
-    const int64_t i = i0[0] + a, j = i0[1] + b, k = i0[2] + c;
-    if (i < 0 || i >= n || j < 0 || j >= n || k < 0 || k >= n) continue;
+    int64_t i = i0[0] + a, j = i0[1] + b, k = i0[2] + c;
+    if (periodic) {
+      i = ((i % n) + n) % n;
+      j = ((j % n) + n) % n;
+      k = ((k % n) + n) % n;
+    } else if (i < 0 || i >= n || j < 0 || j >= n || k < 0 || k >= n) {
+      continue;
+    }
     const double w = (a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1]) * (c ? f[2] : 1.0 - f[2]);
     atomicAdd(&buf[(i * M + j) * M + k].x, m * w);
   }
@@ -179,6 +188,80 @@ __global__ __launch_bounds__(256) void pm_spline_z_kernel(const double* __restri
   for (int k = n - 3; k >= 1; --k) y2[k] = y2[k] - cp[k] * y2[k + 1];
 }
 
+// Periodic box: b = G_q(k) a for the node masses' transform a, with the
+// continuum Green's function of Poisson's equation, phi_k = -4 pi G rho_k / k^2
+// (rho = mass / h^3, k = 0 removed, which also removes the mean density), and
+// dphi/dx_j = i k_j phi_k.  Frequencies in the FFT's order: index i means
+// i / (n h) for i < n/2 and (i - n) / (n h) otherwise.
+__global__ void pm_poisson_kernel(double2* b, const double2* __restrict__ a, int n, double h, int q, double G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (idx >= nn * n) return;
+  const int i = (int)(idx / nn), j = (int)((idx / n) % n), k = (int)(idx % n);
+  const double w = 2.0 * M_PI / (n * h);
+  const double kx = (i < n / 2 ? i : i - n) * w, ky = (j < n / 2 ? j : j - n) * w, kz = (k < n / 2 ? k : k - n) * w;
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  double2 out = make_double2(0.0, 0.0);
+  if (k2 > 0.0) {
+    const double g = -4.0 * M_PI * G / (h * h * h) / k2;
+    const double2 phik = make_double2(g * a[idx].x, g * a[idx].y);
+    if (q == 0) {
+      out = phik;
+    } else {
+      const double kq = q == 1 ? kx : (q == 2 ? ky : kz);
+      out = make_double2(-kq * phik.y, kq * phik.x);   // i k_q phi_k
+    }
+  }
+  b[idx] = out;
+}
+
+// Periodic cubic-spline second derivatives along each x^3 line: the cyclic
+// system y2[k-1] + 4 y2[k] + y2[k+1] = 6 (y[k+1] - 2 y[k] + y[k-1]) / h^2,
+// indices mod n, by the Sherman-Morrison form of elimination: the tridiagonal
+// part with modified corner pivots is solved for the right-hand side and for
+// the corner vector (the latter, like the pivots, is the same for every line
+// and is kept in LDS).
+__global__ __launch_bounds__(256) void pm_spline_z_periodic_kernel(const double* __restrict__ F, double* F2, int n,
+                                                                   double h, int64_t n_lines) {
+  __shared__ double piv[kMaxLine];   // 1 / (diagonal - previous multiplier)
+  __shared__ double zc[kMaxLine];    // solution for the corner vector
+  __shared__ double fz;              // 1 + z[0] + z[n-1] / gamma
+  constexpr double gamma = -4.0;
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double diag = (k == 0) ? 4.0 - gamma : ((k == n - 1) ? 4.0 - 1.0 / gamma : 4.0);
+      const double pk = 1.0 / (diag - (k > 0 ? c : 0.0));
+      piv[k] = pk;
+      c = pk;                         // super-diagonal 1 times the pivot inverse
+    }
+    // corner vector u = (gamma, 0, ..., 0, 1)
+    double d = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double r = (k == 0) ? gamma : ((k == n - 1) ? 1.0 : 0.0);
+      d = (r - (k > 0 ? d : 0.0)) * piv[k];
+      zc[k] = d;
+    }
+    for (int k = n - 2; k >= 0; --k) zc[k] = zc[k] - piv[k] * zc[k + 1];
+    fz = 1.0 + zc[0] + zc[n - 1] / gamma;
+  }
+  __syncthreads();
+  const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= n_lines) return;
+  const double* y = F + line * n;
+  double* y2 = F2 + line * n;
+  const double s = 6.0 / (h * h);
+  double d = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double r = s * (y[(k + 1) % n] - 2.0 * y[k] + y[(k + n - 1) % n]);
+    d = (r - (k > 0 ? d : 0.0)) * piv[k];
+    y2[k] = d;
+  }
+  for (int k = n - 2; k >= 0; --k) y2[k] = y2[k] - piv[k] * y2[k + 1];
+  const double fact = (y2[0] + y2[n - 1] / gamma) / fz;
+  for (int k = 0; k < n; ++k) y2[k] = y2[k] - fact * zc[k];
+}
+
 // ------------------------------------------------------------------ App. B evaluation
 __device__ __forceinline__ double spline_eval(double yk, double yk1, double y2k, double y2k1, double A, double h) {
   const double B = 1.0 - A;
@@ -233,12 +316,63 @@ __device__ __forceinline__ int window_start(double u, int n, int NI) {
 struct PmGrid {
   int n;
   double ox, oy, oz, h;
+  int periodic;
 };
+
+__device__ __forceinline__ int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+// App. B on a periodic grid: the point is brought into the box (fmod, then + n
+// for negative values), the x^3 segment and the x^1, x^2 windows are taken
+// modulo n; the local splines see the unwrapped window nodes.
+template <int NI>
+__device__ void pm_field_periodic(const PmGrid& g, const double* __restrict__ fields, double x, double y, double z,
+                                  double& phi, double& gx, double& gy, double& gz) {
+  const int n = g.n;
+  const double dn = (double)n;
+  double ux = fmod((x - g.ox) / g.h, dn), uy = fmod((y - g.oy) / g.h, dn), uz = fmod((z - g.oz) / g.h, dn);
+  phi = gx = gy = gz = 0.0;
+  if (!(isfinite(ux) && isfinite(uy) && isfinite(uz))) return;
+  if (ux < 0.0) ux += dn;
+  if (uy < 0.0) uy += dn;
+  if (uz < 0.0) uz += dn;
+  const int fx = (int)floor(ux), fy = (int)floor(uy), fz = (int)floor(uz);
+  const int wx = fx - NI + 1, wy = fy - NI + 1;
+  const int kz0 = wrap(fz, n), kz1 = wrap(fz + 1, n);
+  const double Az = (double)(fz + 1) - uz;
+  const int64_t n3 = (int64_t)n * n * n;
+  double out[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double* F = fields + q * n3;
+    const double* F2 = fields + (q + 4) * n3;
+    double w[2 * NI];
+#pragma unroll
+    for (int b = 0; b < 2 * NI; ++b) {
+      const int j = wrap(wy + b, n);
+      double v[2 * NI];
+#pragma unroll
+      for (int a = 0; a < 2 * NI; ++a) {
+        const int64_t row = ((int64_t)wrap(wx + a, n) * n + j) * n;
+        v[a] = spline_eval(F[row + kz0], F[row + kz1], F2[row + kz0], F2[row + kz1], Az, g.h);
+      }
+      w[b] = local_spline<NI>(v, wx, ux, g.h);
+    }
+    out[q] = local_spline<NI>(w, wy, uy, g.h);
+  }
+  phi = out[0];
+  gx = out[1];
+  gy = out[2];
+  gz = out[3];
+}
 
 // The four grid quantities at (x, y, z): phi and its gradient.
 template <int NI>
 __device__ void pm_field(const PmGrid& g, const double* __restrict__ fields, double x, double y, double z, double& phi,
                          double& gx, double& gy, double& gz) {
+  if (g.periodic) {
+    pm_field_periodic<NI>(g, fields, x, y, z, phi, gx, gy, gz);
+    return;
+  }
   const int n = g.n;
   const double ux = (x - g.ox) / g.h, uy = (y - g.oy) / g.h, uz = (z - g.oz) / g.h;
   phi = gx = gy = gz = 0.0;
@@ -433,14 +567,14 @@ inline unsigned blocks_for(int64_t count, int threads) { return (unsigned)((coun
 
 }  // namespace
 
-int64_t pm_workspace_bytes(int n) {
-  const int64_t M = 2 * (int64_t)n;
+int64_t pm_workspace_bytes(int n, int periodic) {
+  const int64_t M = periodic ? (int64_t)n : 2 * (int64_t)n;
   return 2 * M * M * M * (int64_t)sizeof(double2) + (M / 2) * (int64_t)sizeof(double2);
 }
 
 hipError_t launch_pm_build(const double* xyzm, int64_t np, double eps, const double origin[3], double h, int n,
-                           double G, double* fields, void* workspace, hipStream_t s) {
-  const int M = 2 * n;
+                           int periodic, double G, double* fields, void* workspace, hipStream_t s) {
+  const int M = periodic ? n : 2 * n;
   int log2M = 0;
   while ((1 << log2M) < M) ++log2M;
   const int64_t M3 = (int64_t)M * M * M;
@@ -453,7 +587,7 @@ hipError_t launch_pm_build(const double* xyzm, int64_t np, double eps, const dou
   hipLaunchKernelGGL(pm_clear_kernel, dim3(blocks_for(M3, 256)), dim3(256), 0, s, A, M3);
   if (np > 0)
     hipLaunchKernelGGL(pm_cic_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, s, xyzm, np, origin[0], origin[1],
-                       origin[2], h, n, M, A);
+                       origin[2], h, n, M, periodic, A);
   auto fft3 = [&](double2* buf, int inverse) {
     for (int axis = 2; axis >= 0; --axis)
       hipLaunchKernelGGL(pm_fft_kernel, dim3((unsigned)((int64_t)M * M)), dim3(fft_threads), 0, s, buf, M, log2M,
@@ -461,22 +595,31 @@ hipError_t launch_pm_build(const double* xyzm, int64_t np, double eps, const dou
   };
   fft3(A, 0);
   for (int q = 0; q < 4; ++q) {
-    hipLaunchKernelGGL(pm_greens_kernel, dim3(blocks_for(M3, 256)), dim3(256), 0, s, B, n, M, h, eps * eps, q, G);
-    fft3(B, 0);
-    hipLaunchKernelGGL(pm_mul_kernel, dim3(blocks_for(M3, 256)), dim3(256), 0, s, B, (const double2*)A, M3);
+    if (periodic) {
+      hipLaunchKernelGGL(pm_poisson_kernel, dim3(blocks_for(M3, 256)), dim3(256), 0, s, B, (const double2*)A, n, h, q,
+                         G);
+    } else {
+      hipLaunchKernelGGL(pm_greens_kernel, dim3(blocks_for(M3, 256)), dim3(256), 0, s, B, n, M, h, eps * eps, q, G);
+      fft3(B, 0);
+      hipLaunchKernelGGL(pm_mul_kernel, dim3(blocks_for(M3, 256)), dim3(256), 0, s, B, (const double2*)A, M3);
+    }
     fft3(B, 1);
     hipLaunchKernelGGL(pm_extract_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, (const double2*)B,
                        fields + q * n3, n, M, 1.0 / (double)M3);
   }
   const int64_t lines = 4 * (int64_t)n * n;
-  hipLaunchKernelGGL(pm_spline_z_kernel, dim3(blocks_for(lines, 256)), dim3(256), 0, s, (const double*)fields,
-                     fields + 4 * n3, n, h, lines);
+  if (periodic)
+    hipLaunchKernelGGL(pm_spline_z_periodic_kernel, dim3(blocks_for(lines, 256)), dim3(256), 0, s,
+                       (const double*)fields, fields + 4 * n3, n, h, lines);
+  else
+    hipLaunchKernelGGL(pm_spline_z_kernel, dim3(blocks_for(lines, 256)), dim3(256), 0, s, (const double*)fields,
+                       fields + 4 * n3, n, h, lines);
   return hipGetLastError();
 }
 
-hipError_t launch_pm_eval(const double origin[3], double h, int n, const double* fields, int n_int, int64_t np,
+hipError_t launch_pm_eval(const double origin[3], double h, int n, int periodic, const double* fields, int n_int, int64_t np,
                           const double* pts, double* phi, double* grad, hipStream_t s) {
-  const PmGrid g{n, origin[0], origin[1], origin[2], h};
+  const PmGrid g{n, origin[0], origin[1], origin[2], h, periodic};
   const dim3 grid(blocks_for(np, 256)), block(256);
   switch (n_int) {
     case 1: hipLaunchKernelGGL(pm_eval_kernel<1>, grid, block, 0, s, g, fields, np, pts, phi, grad); break;
@@ -487,10 +630,10 @@ hipError_t launch_pm_eval(const double origin[3], double h, int n, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_pm_trace(DevCosmo c, const double origin[3], double h, int n, const double* fields, int n_int,
+hipError_t launch_pm_trace(DevCosmo c, const double origin[3], double h, int n, int periodic, const double* fields, int n_int,
                            const double* nodes, int32_t step_begin, int32_t step_end, double* rays, int64_t n_rays,
                            uint8_t* flags, hipStream_t s) {
-  const PmGrid g{n, origin[0], origin[1], origin[2], h};
+  const PmGrid g{n, origin[0], origin[1], origin[2], h, periodic};
   const dim3 grid(blocks_for(n_rays, 256)), block(256);
   switch (n_int) {
     case 1:
@@ -513,10 +656,10 @@ hipError_t launch_pm_trace(DevCosmo c, const double origin[3], double h, int n, 
   return hipGetLastError();
 }
 
-hipError_t launch_pm_trace_lambda(DevCosmo c, const double origin[3], double h, int n, const double* fields,
+hipError_t launch_pm_trace_lambda(DevCosmo c, const double origin[3], double h, int n, int periodic, const double* fields,
                                   int n_int, double chi_s, double f_rk, int32_t max_steps, double* rays,
                                   int64_t n_rays, uint8_t* flags, int32_t* steps, hipStream_t s) {
-  const PmGrid g{n, origin[0], origin[1], origin[2], h};
+  const PmGrid g{n, origin[0], origin[1], origin[2], h, periodic};
   const dim3 grid(blocks_for(n_rays, 256)), block(256);
   switch (n_int) {
     case 1:

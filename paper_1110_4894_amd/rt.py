@@ -57,7 +57,7 @@ class rt_trace_info(C.Structure):
 
 
 class rt_pm_grid(C.Structure):
-    _fields_ = [("n", C.c_int32), ("origin", C.c_double * 3), ("h", C.c_double)]
+    _fields_ = [("n", C.c_int32), ("origin", C.c_double * 3), ("h", C.c_double), ("periodic", C.c_int32)]
 
 
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
@@ -280,8 +280,8 @@ def rt_release_caches():
     load().rt_release_caches()
 
 
-def pm_grid(n: int, origin, h: float) -> rt_pm_grid:
-    return rt_pm_grid(int(n), (C.c_double * 3)(*[float(v) for v in origin]), float(h))
+def pm_grid(n: int, origin, h: float, periodic: bool = False) -> rt_pm_grid:
+    return rt_pm_grid(int(n), (C.c_double * 3)(*[float(v) for v in origin]), float(h), 1 if periodic else 0)
 
 
 def rt_pm_workspace_bytes(grid: rt_pm_grid) -> int:

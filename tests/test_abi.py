@@ -159,3 +159,11 @@ def test_pm_argument_errors(lib):
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 2, 0.5, 0, 2, fake) == -1
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, around, fake, 2, 0.5, 100, 2, fake) == -1
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 9, 0.5, 100, 2, fake) == -1
+    # periodic boxes: smaller workspace (no padding), no traces
+    pg = rt.pm_grid(32, (-1.0, -1.0, 999.0), 0.0625, periodic=True)
+    assert rt.rt_pm_workspace_bytes(pg) == 32 * 32 ** 3 + 8 * 32
+    bad = rt.pm_grid(32, (0, 0, 0), 0.1)
+    bad.periodic = 2
+    assert _status(rt.rt_pm_workspace_bytes, bad) == -1
+    assert _status(rt.rt_trace_pm, c, 0.5, pg, fake, 2, nodes, 0, 10, 2, fake) == -7
+    assert _status(rt.rt_trace_pm_lambda, c, 0.5, pg, fake, 2, 0.5, 100, 2, fake) == -7

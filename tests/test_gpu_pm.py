@@ -199,3 +199,62 @@ def test_lambda_integrator_matches_oracle():
     rt.rt_trace_pm_lambda(c, z_s, grid, fields, 2, 2.0, 100, nb, rays, flags)
     torch.cuda.synchronize()
     assert np.all(flags.cpu().numpy() == 8) and np.all(rays.cpu().numpy()[3] < chi_s)
+
+
+def _build_periodic(xyz, m, n, origin, h):
+    dev = torch.device("cuda")
+    xyzm = torch.from_numpy(np.ascontiguousarray(np.concatenate([xyz.T, m[None]], 0))).to(dev)
+    pset = rt.make_particle_set(xyzm, softening=0.0, background=True, lo=(0, 0, 0), hi=(1, 1, 1))
+    grid = rt.pm_grid(n, origin, h, periodic=True)
+    nb = rt.rt_pm_workspace_bytes(grid)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    fields = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+    print("    [pm] periodic build n=%d, %d particles" % (n, len(m)), flush=True)
+    rt.rt_pm_build(pset, grid, fields, ws, nb)
+    torch.cuda.synchronize()
+    return grid, fields
+
+
+@pytest.mark.parametrize("n", [8, 32])
+def test_periodic_pm_build_matches_oracle(n):
+    """A clustered periodic box (particles also outside the first period, wrapped)."""
+    h = 0.1
+    L = n * h
+    origin = np.array([-0.5 * L, -0.5 * L, 30.0])
+    rng = np.random.default_rng(n)
+    xyz = origin + np.mod(rng.normal(0.5 * L, 0.2 * L, (4000, 3)), 1.5 * L) - 0.25 * L
+    m = rng.uniform(0.5, 1.5, 4000) * 1e10
+    grid, fields = _build_periodic(xyz, m, n, origin, h)
+    got = fields.cpu().numpy()
+    want = opm.periodic_field(opm.cic_deposit_periodic(xyz, m, origin, h, n), h)
+    for q in range(4):
+        assert np.max(np.abs(got[q] - want[q])) <= 1e-11 * np.abs(want[q]).max(), q
+    y2 = opm.spline_y2_periodic(got[:4], h)
+    for q in range(4):
+        assert np.max(np.abs(got[4 + q] - y2[q])) <= 1e-12 * np.abs(y2[q]).max(), q
+
+
+@pytest.mark.parametrize("n_int", [1, 2, 3, 4])
+def test_periodic_pm_eval_matches_oracle_on_the_same_grids(n_int):
+    n, h = 16, 0.1
+    L = n * h
+    origin = np.array([-0.8, -0.8, 10.0])
+    rng = np.random.default_rng(30 + n_int)
+    xyz = origin + rng.uniform(0, L, (2000, 3))
+    m = np.full(2000, 1e10)
+    grid, fields = _build_periodic(xyz, m, n, origin, h)
+    F = fields.cpu().numpy()
+    u = np.concatenate([rng.uniform(0, n, (150, 3)), rng.integers(0, n, (20, 3)).astype(float),
+                        rng.uniform(-2 * n, 3 * n, (50, 3)), np.array([[n - 1e-9, 0.0, n - 0.5], [-1e-12, 5.0, 2.0]])])
+    pts = (origin + u * h).T.copy()
+    dev = torch.device("cuda")
+    P = torch.from_numpy(pts).to(dev)
+    phi = torch.empty(pts.shape[1], dtype=torch.float64, device=dev)
+    grad = torch.empty((3, pts.shape[1]), dtype=torch.float64, device=dev)
+    rt.rt_pm_eval(grid, fields, n_int, pts.shape[1], P, phi, grad)
+    torch.cuda.synchronize()
+    got = np.concatenate([phi.cpu().numpy()[None], grad.cpu().numpy()])
+    want = np.array([opm.appb_eval_periodic(F[:4], F[4:], origin, h, n_int, pts[:, i])
+                     for i in range(pts.shape[1])]).T
+    for q in range(4):
+        assert np.max(np.abs(got[q] - want[q])) <= 1e-12 * np.abs(F[q]).max(), q

@@ -217,3 +217,79 @@ def test_lambda_integrator_converges_to_the_z_integrator():
         errs.append(max(np.max(np.hypot(out[1] - ref[1], out[2] - ref[2]) / defl), abs(mu[0] / mu_ref[0] - 1)))
     assert errs[1] < 1e-3
     assert errs[0] > 20 * errs[1]
+
+
+def test_periodic_deposit_wraps_and_conserves_mass():
+    n, h, origin = 8, 0.5, np.zeros(3)
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(-2.0, 6.0, (300, 3))                 # also outside the first period
+    m = rng.uniform(1, 2, 300)
+    g = pm.cic_deposit_periodic(xyz, m, origin, h, n)
+    assert g.sum() == pytest.approx(m.sum(), rel=1e-14)
+    # a particle half a cell below the upper face shares its mass with node 0 (wrap)
+    g1 = pm.cic_deposit_periodic(np.array([[3.75, 0.0, 0.0]]), np.array([2.0]), origin, h, n)
+    assert g1[7, 0, 0] == 1.0 and g1[0, 0, 0] == 1.0
+    # shifting every particle by one period changes nothing
+    g2 = pm.cic_deposit_periodic(xyz + np.array([4.0, -4.0, 8.0]), m, origin, h, n)
+    assert np.allclose(g2, g, rtol=0, atol=1e-12)
+
+
+def test_periodic_field_of_a_single_mode_is_the_poisson_solution():
+    """Node masses M0 (1 + A cos(k x)): phi = -4 pi G A (M0 / h^3) cos(k x) / k^2 and
+    dphi/dx = 4 pi G A (M0 / h^3) sin(k x) / k, exactly on the nodes; no mean term."""
+    n, h = 16, 0.25
+    L = n * h
+    x = np.arange(n) * h
+    for mode, A in [(1, 0.3), (3, -0.1)]:
+        k = 2 * np.pi * mode / L
+        M0 = 1e11
+        mass = np.broadcast_to((M0 * (1 + A * np.cos(k * x)))[:, None, None], (n, n, n)).copy()
+        f = pm.periodic_field(mass, h)
+        G = orc.G_over_c2()
+        amp = 4 * np.pi * G * A * M0 / h ** 3
+        tol = 1e-12 * abs(amp)
+        assert np.allclose(f[0][:, 3, 5], -amp * np.cos(k * x) / k ** 2, rtol=0, atol=tol / k ** 2)
+        assert np.allclose(f[1][:, 3, 5], amp * np.sin(k * x) / k, rtol=0, atol=tol / k)
+        assert np.max(np.abs(f[2])) < tol / k and np.max(np.abs(f[3])) < tol / k
+    rng = np.random.default_rng(3)
+    f = pm.periodic_field(rng.uniform(0, 1e10, (n, n, n)), h)
+    assert abs(f[0].mean()) < 1e-12 * np.abs(f[0]).max()
+
+
+def test_periodic_spline_is_scipys_periodic_spline():
+    rng = np.random.default_rng(5)
+    y = rng.normal(size=(2, 12))
+    h = 0.3
+    y2 = pm.spline_y2_periodic(y, h)
+    x = np.arange(13) * h
+    for r in range(2):
+        cs = CubicSpline(x, np.append(y[r], y[r][0]), bc_type="periodic")
+        assert np.allclose(y2[r], cs(x[:-1], 2), rtol=0, atol=1e-10)
+
+
+def test_periodic_appb_wraps_and_is_exact_on_nodes():
+    n, h, origin = 12, 0.25, np.array([-1.5, -1.5, 40.0])
+    rng = np.random.default_rng(6)
+    F = np.stack([rng.normal(size=(n, n, n)) for _ in range(4)])
+    F2 = pm.spline_y2_periodic(F, h)
+    for n_int in (1, 2, 3):
+        for ijk in [(0, 0, 0), (11, 5, 11), (3, 0, 7)]:
+            p = origin + h * np.array(ijk)
+            assert np.allclose(pm.appb_eval_periodic(F, F2, origin, h, n_int, p), F[(slice(None),) + ijk],
+                               rtol=0, atol=1e-12)
+        for _ in range(5):
+            p = origin + rng.uniform(0, n, 3) * h
+            a = pm.appb_eval_periodic(F, F2, origin, h, n_int, p)
+            b = pm.appb_eval_periodic(F, F2, origin, h, n_int, p + n * h * np.array([1, -2, 3]))
+            assert np.allclose(a, b, rtol=0, atol=1e-12)
+    # a smooth periodic field is interpolated to second order
+    L = n * h
+    fn = lambda X, Y, Z: np.sin(2 * np.pi * (X - origin[0]) / L) * np.cos(2 * np.pi * (Z - origin[2]) / L)
+    errs = []
+    for nn in (16, 32):
+        hh = L / nn
+        G = np.stack([_grid_of(fn, nn, hh, origin)] * 4)
+        G2 = pm.spline_y2_periodic(G, hh)
+        pts = origin + np.random.default_rng(1).uniform(0, L, (20, 3))
+        errs.append(max(abs(pm.appb_eval_periodic(G, G2, origin, hh, 2, q)[0] - fn(*q)) for q in pts))
+    assert 3.2 < errs[0] / errs[1] < 20
