@@ -49,7 +49,8 @@ FLOP_PER_INTERACTION = 20.0
 # 1.0), keyed by the sha256 prefix of the kernel sources they were taken with
 # (kernel_source_sha; the first two entries hashed rt_kernels.hip alone).
 MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0},
-                    "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0,
+                    "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0},
+                    "d9ecd4450456f251": {"read": 791484190955.2822, "write": 309593703488.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 

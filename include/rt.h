@@ -210,23 +210,30 @@ rt_status rt_pm_build(const rt_particle_set* set, const rt_pm_grid* grid, double
 rt_status rt_pm_eval(const rt_pm_grid* grid, const double* fields, int32_t n_int, int64_t n, const double* points,
                      double* phi, double* grad, hipStream_t stream);
 
-/* rt_trace with the field of a built isolated grid in place of the direct sum (one field, every
- * step; RT_ERR_UNSUPPORTED for a periodic grid):
- * the same RK4 in z over z_nodes (host [n_steps + 1], 0 to chi_s), the same Christoffel
- * contraction, exit and flags.  The observer (0, 0, 0) must lie outside the grid's node box, so
- * that the potential there is 0 as for bundles built by rt_build_bundles with no mass at step 0.
- * rays: device [8][9 n_bundles], in and out; ray_flags: device [9 n_bundles] or NULL. */
-rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid, const double* fields,
-                      int32_t n_int, int32_t n_steps, const double* z_nodes, int32_t step_begin, int32_t step_end,
-                      int64_t n_bundles, double* rays, uint8_t* ray_flags, hipStream_t stream);
+/* rt_trace with the field of built grids in place of the direct sum: the same RK4 in z over
+ * z_nodes (host [n_steps + 1], 0 to chi_s), the same Christoffel contraction, exit and flags;
+ * all four stages of step s use grid step_grid[s] (host [n_steps], -1 = no field; NULL = grid 0
+ * at every step), as the direct path uses a particle set per step: one isolated grid for a lens,
+ * one periodic grid per box replica for a light cone.  grids: host [n_grids]; fields: host
+ * [n_grids] of device pointers to built fields; n_int as for rt_pm_eval (valid for every grid).
+ * An isolated grid must leave the observer (0, 0, 0) outside its nodes, so that its potential
+ * there is the 0 used by bundles built with no mass at step 0; for periodic grids the caller
+ * builds the bundles with the potential it wants at the observer (e.g. rt_build_bundles over the
+ * same particle sets).  rays: device [8][9 n_bundles], in and out; ray_flags: device
+ * [9 n_bundles] or NULL. */
+rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, int32_t n_grids, const rt_pm_grid* grids,
+                      const double* const* fields, int32_t n_int, int32_t n_steps, const double* z_nodes,
+                      const int32_t* step_grid, int32_t step_begin, int32_t step_end, int64_t n_bundles,
+                      double* rays, uint8_t* ray_flags, hipStream_t stream);
 
 /* The paper's own integrator (Sec. 3.4, eq. RKstepsize) through a built grid: classical RK4 in
  * the affine parameter with the fixed step d_lambda = f_rk h / kz_0 per ray (h = grid.h, the
  * L_box / n_FFT of the paper; kz_0 = the ray's kz on entry), repeated until z reaches chi_s;
  * the step that overshoots is replaced by the linear interpolation between the previous and
  * the current state at z = chi_s (all eight components).  A ray that has not reached chi_s
- * after max_steps keeps its last state and is flagged 8.  f_rk > 0, max_steps >= 1; the
- * observer must lie outside the grid as for rt_trace_pm.  rays: device [8][9 n_bundles], in and
+ * after max_steps keeps its last state and is flagged 8.  f_rk > 0, max_steps >= 1; the grid
+ * must be isolated (RT_ERR_UNSUPPORTED for a periodic one) and leave the observer outside its
+ * nodes, as for rt_trace_pm.  rays: device [8][9 n_bundles], in and
  * out (z on entry < chi_s); ray_flags: device [9 n_bundles] or NULL (1, 2, 4 as for rt_trace,
  * 8 as above); ray_steps: device int32 [9 n_bundles] or NULL, steps taken per ray. */
 rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid,

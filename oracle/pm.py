@@ -227,10 +227,18 @@ def pm_field(xyz, m, eps, origin, h, n, n_int, points):
 
 
 def trace_pm(c, nodes, rays, fields, fields_y2z, origin, h, n_int, step_begin=0, step_end=2 ** 31 - 1):
+    """trace_pm_steps with one isolated grid used at every step."""
+    grid = (fields, fields_y2z, origin, h, False)
+    return trace_pm_steps(c, nodes, rays, [grid], np.zeros(len(nodes) - 1, dtype=np.int64), n_int, step_begin,
+                          step_end)
+
+
+def trace_pm_steps(c, nodes, rays, grids, step_grid, n_int, step_begin=0, step_end=2 ** 31 - 1):
     """Classical RK4 in z over the given nodes (Sec. 3.4 with x^3 as the independent
-    variable), the field at every stage from the grid by App. B; same flags as the direct
-    oracle: 1 non-finite, 2 k^z <= 0 (both freeze the ray), 4 |phi|/a > 1e-2.
-    rays [8, R] (t, x, y, z, kt, kx, ky, kz) are updated in place; returns (rays, flags)."""
+    variable); all four stages of step s take the field of grid step_grid[s] by App. B
+    (none for -1).  grids: list of (fields [4,n,n,n], x^3 splines [4,n,n,n], origin, h,
+    periodic).  Same flags as the direct oracle: 1 non-finite, 2 k^z <= 0 (both freeze the
+    ray), 4 |phi|/a > 1e-2.  rays [8, R] are updated in place; returns (rays, flags)."""
     from . import derivs, scale_factor
     n_steps = len(nodes) - 1
     flags = np.zeros(rays.shape[1], dtype=np.uint8)
@@ -240,9 +248,15 @@ def trace_pm(c, nodes, rays, fields, fields_y2z, origin, h, n_int, step_begin=0,
         for s in range(step_begin, min(step_end, n_steps)):
             Z0, Z1 = nodes[s], nodes[s + 1]
             hs = Z1 - Z0
+            gi = int(step_grid[s])
 
             def f(Yv, zz):
-                q = appb_eval(fields, fields_y2z, origin, h, n_int, [Yv[1], Yv[2], zz])
+                if gi < 0:
+                    q = np.zeros(4)
+                else:
+                    F, F2, org, hh, periodic = grids[gi]
+                    ev = appb_eval_periodic if periodic else appb_eval
+                    q = ev(F, F2, org, hh, n_int, [Yv[1], Yv[2], zz])
                 return derivs(c, Yv, q[0], q[1:]), q[0]
 
             k1, phi0 = f(Y, Z0)

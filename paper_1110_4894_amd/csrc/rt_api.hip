@@ -892,10 +892,9 @@ rt_status check_pm_grid(const rt_pm_grid* g) {
   return RT_OK;
 }
 
-// The grids' potential at the observer must be 0 (bundles are built with phi_obs = 0),
-// so traces take isolated grids that leave the observer outside their nodes.
+// An isolated grid's potential at the observer must be 0 (bundles are built with
+// phi_obs = 0 there), so it must leave the observer outside its nodes.
 rt_status check_observer_outside(const rt_pm_grid* g) {
-  if (g->periodic) return fail(RT_ERR_UNSUPPORTED, "traces through a periodic grid are not supported");
   bool inside = true;
   for (int d = 0; d < 3; ++d) {
     const double lo = g->origin[d], hi = g->origin[d] + g->h * (g->n - 1);
@@ -951,16 +950,22 @@ rt_status rt_pm_eval(const rt_pm_grid* grid, const double* fields, int32_t n_int
   return RT_OK;
 }
 
-rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid, const double* fields,
-                      int32_t n_int, int32_t n_steps, const double* z_nodes, int32_t step_begin, int32_t step_end,
-                      int64_t n_bundles, double* rays, uint8_t* ray_flags, hipStream_t stream) {
+rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, int32_t n_grids, const rt_pm_grid* grids,
+                      const double* const* fields, int32_t n_int, int32_t n_steps, const double* z_nodes,
+                      const int32_t* step_grid, int32_t step_begin, int32_t step_end, int64_t n_bundles, double* rays,
+                      uint8_t* ray_flags, hipStream_t stream) {
   rt_status st;
   if ((st = check_cosmo(cosmo)) != RT_OK) return st;
   if (!std::isfinite(z_source)) return fail(RT_ERR_NONFINITE, "z_source is not finite");
   if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
-  if ((st = check_pm_grid(grid)) != RT_OK) return st;
-  if ((st = check_n_int(grid, n_int)) != RT_OK) return st;
-  if (!fields) return fail(RT_ERR_INVALID_ARG, "fields is NULL");
+  if (n_grids < 1 || !grids || !fields) return fail(RT_ERR_INVALID_ARG, "n_grids < 1, or grids or fields is NULL");
+  for (int i = 0; i < n_grids; ++i) {
+    if ((st = check_pm_grid(&grids[i])) != RT_OK) return fail(st, "grids[%d]: %s", i, g_err.c_str());
+    if ((st = check_n_int(&grids[i], n_int)) != RT_OK) return fail(st, "grids[%d]: %s", i, g_err.c_str());
+    if (!fields[i]) return fail(RT_ERR_INVALID_ARG, "fields[%d] is NULL", i);
+    if (!grids[i].periodic && (st = check_observer_outside(&grids[i])) != RT_OK)
+      return fail(st, "grids[%d]: %s", i, g_err.c_str());
+  }
   if (n_bundles < 0) return fail(RT_ERR_INVALID_ARG, "n_bundles < 0");
   if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
   if (step_begin < 0 || step_end < step_begin) return fail(RT_ERR_INVALID_ARG, "bad step window");
@@ -973,16 +978,39 @@ rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, const rt_pm_gr
   }
   if (std::fabs(z_nodes[n_steps] - chi_s) > 1e-9 * chi_s)
     return fail(RT_ERR_SCHEDULE, "last node %.17g differs from chi_s %.17g", z_nodes[n_steps], chi_s);
-  if ((st = check_observer_outside(grid)) != RT_OK) return st;
+  std::vector<int32_t> sg(n_steps, 0);
+  if (step_grid) {
+    for (int s = 0; s < n_steps; ++s) {
+      if (step_grid[s] < -1 || step_grid[s] >= n_grids)
+        return fail(RT_ERR_INVALID_ARG, "step_grid[%d] = %d out of [-1, %d)", s, step_grid[s], n_grids);
+      sg[s] = step_grid[s];
+    }
+  }
   const int32_t se = step_end > n_steps ? n_steps : step_end;
   if (n_bundles == 0 || step_begin >= se) return RT_OK;
-  double* d_nodes = nullptr;
-  RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_nodes), sizeof(double) * (n_steps + 1), stream));
+  std::vector<DevPmGrid> hg(n_grids);
+  for (int i = 0; i < n_grids; ++i) {
+    hg[i].n = grids[i].n;
+    for (int d = 0; d < 3; ++d) hg[i].origin[d] = grids[i].origin[d];
+    hg[i].h = grids[i].h;
+    hg[i].periodic = grids[i].periodic;
+    hg[i].fields = fields[i];
+  }
+  // scratch: grid table, then nodes, then step grids
+  const size_t gbytes = ((sizeof(DevPmGrid) * n_grids + 255) / 256) * 256;
+  const size_t nbytes = ((sizeof(double) * (n_steps + 1) + 255) / 256) * 256;
+  char* scratch = nullptr;
+  RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), gbytes + nbytes + sizeof(int32_t) * n_steps, stream));
+  DevPmGrid* d_grids = reinterpret_cast<DevPmGrid*>(scratch);
+  double* d_nodes = reinterpret_cast<double*>(scratch + gbytes);
+  int32_t* d_sg = reinterpret_cast<int32_t*>(scratch + gbytes + nbytes);
+  RT_HIP(hipMemcpyAsync(d_grids, hg.data(), sizeof(DevPmGrid) * n_grids, hipMemcpyHostToDevice, stream));
   RT_HIP(hipMemcpyAsync(d_nodes, z_nodes, sizeof(double) * (n_steps + 1), hipMemcpyHostToDevice, stream));
-  RT_HIP(hipStreamSynchronize(stream));   // z_nodes is pageable host memory owned by the caller
-  RT_HIP(launch_pm_trace(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, grid->periodic, fields, n_int, d_nodes,
-                         step_begin, se, rays, 9 * n_bundles, ray_flags, stream));
-  RT_HIP(hipFreeAsync(d_nodes, stream));
+  RT_HIP(hipMemcpyAsync(d_sg, sg.data(), sizeof(int32_t) * n_steps, hipMemcpyHostToDevice, stream));
+  RT_HIP(hipStreamSynchronize(stream));   // the host staging above is pageable and local
+  RT_HIP(launch_pm_trace(make_dev_cosmo(*cosmo), d_grids, d_sg, n_int, d_nodes, step_begin, se, rays,
+                         9 * n_bundles, ray_flags, stream));
+  RT_HIP(hipFreeAsync(scratch, stream));
   return RT_OK;
 }
 
@@ -1001,6 +1029,7 @@ rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const r
   if (max_steps < 1) return fail(RT_ERR_INVALID_ARG, "max_steps must be >= 1");
   if (n_bundles < 0) return fail(RT_ERR_INVALID_ARG, "n_bundles < 0");
   if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
+  if (grid->periodic) return fail(RT_ERR_UNSUPPORTED, "rt_trace_pm_lambda takes an isolated grid");
   if ((st = check_observer_outside(grid)) != RT_OK) return st;
   if (n_bundles == 0) return RT_OK;
   RT_HIP(launch_pm_trace_lambda(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, grid->periodic, fields, n_int,

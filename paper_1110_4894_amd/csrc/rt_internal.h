@@ -77,14 +77,21 @@ hipError_t launch_histogram(int64_t n, const double* mu, const double* jac, int 
                             double hi, double* pdf, double* moments, double* work, hipStream_t s);
 
 // Particle-mesh field (rt_pm.hip).
+struct DevPmGrid {
+  int32_t n;
+  double origin[3];
+  double h;
+  int32_t periodic;
+  const double* fields;   // [8][n^3]
+};
 int64_t pm_workspace_bytes(int n, int periodic);
 hipError_t launch_pm_build(const double* xyzm, int64_t np, double eps, const double origin[3], double h, int n,
                            int periodic, double G, double* fields, void* workspace, hipStream_t s);
 hipError_t launch_pm_eval(const double origin[3], double h, int n, int periodic, const double* fields, int n_int,
                           int64_t np, const double* pts, double* phi, double* grad, hipStream_t s);
-hipError_t launch_pm_trace(DevCosmo c, const double origin[3], double h, int n, int periodic, const double* fields,
-                           int n_int, const double* nodes, int32_t step_begin, int32_t step_end, double* rays,
-                           int64_t n_rays, uint8_t* flags, hipStream_t s);
+hipError_t launch_pm_trace(DevCosmo c, const DevPmGrid* grids, const int32_t* step_grid, int n_int,
+                           const double* nodes, int32_t step_begin, int32_t step_end, double* rays, int64_t n_rays,
+                           uint8_t* flags, hipStream_t s);
 hipError_t launch_pm_trace_lambda(DevCosmo c, const double origin[3], double h, int n, int periodic,
                                   const double* fields, int n_int, double chi_s, double f_rk, int32_t max_steps,
                                   double* rays, int64_t n_rays, uint8_t* flags, int32_t* steps, hipStream_t s);

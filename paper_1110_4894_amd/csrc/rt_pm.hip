@@ -421,9 +421,12 @@ __global__ __launch_bounds__(256) void pm_eval_kernel(PmGrid g, const double* __
 
 // ------------------------------------------------------------------ trace through the PM field
 // One ray per thread; the same RK4 in z, Christoffel contraction and flags as
-// the direct-sum trace kernel, with the field taken from the grid.
+// the direct-sum trace kernel, with the field of step s taken from grid
+// step_grid[s] (none for -1): one isolated grid for a lens, one periodic grid
+// per box replica for a light cone.
 template <int NI>
-__global__ __launch_bounds__(256) void pm_trace_kernel(DevCosmo cz, PmGrid g, const double* __restrict__ fields,
+__global__ __launch_bounds__(256) void pm_trace_kernel(DevCosmo cz, const DevPmGrid* __restrict__ grids,
+                                                       const int32_t* __restrict__ step_grid,
                                                        const double* __restrict__ nodes, int32_t step_begin,
                                                        int32_t step_end, double* rays, int64_t N, uint8_t* flags) {
   const int64_t ri = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -436,14 +439,22 @@ __global__ __launch_bounds__(256) void pm_trace_kernel(DevCosmo cz, PmGrid g, co
   for (int s = step_begin; s < step_end && live; ++s) {
     const double Z0 = nodes[s], Z1 = nodes[s + 1];
     const double h = Z1 - Z0, hh = 0.5 * h;
+    const int gi = step_grid[s];
+    PmGrid g{0, 0.0, 0.0, 0.0, 1.0, 0};
+    const double* fields = nullptr;
+    if (gi >= 0) {
+      const DevPmGrid d = grids[gi];
+      g = PmGrid{d.n, d.origin[0], d.origin[1], d.origin[2], d.h, d.periodic};
+      fields = d.fields;
+    }
     State acc, Ys, k;
     double a;
 #pragma unroll 1
     for (int stage = 0; stage < 4; ++stage) {
       const State& Yin = (stage == 0) ? Y : Ys;
       const double zs = (stage == 0) ? Z0 : ((stage == 3) ? Z1 : Z0 + hh);
-      double phi, gx, gy, gz;
-      pm_field<NI>(g, fields, Yin.x, Yin.y, zs, phi, gx, gy, gz);
+      double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+      if (gi >= 0) pm_field<NI>(g, fields, Yin.x, Yin.y, zs, phi, gx, gy, gz);
       k = rhs(cz, Yin, phi, gx, gy, gz, a);
       if (stage == 0) {
         if (fabs(phi) / a > 1e-2) flag |= 4;
@@ -630,27 +641,26 @@ hipError_t launch_pm_eval(const double origin[3], double h, int n, int periodic,
   return hipGetLastError();
 }
 
-hipError_t launch_pm_trace(DevCosmo c, const double origin[3], double h, int n, int periodic, const double* fields, int n_int,
+hipError_t launch_pm_trace(DevCosmo c, const DevPmGrid* grids, const int32_t* step_grid, int n_int,
                            const double* nodes, int32_t step_begin, int32_t step_end, double* rays, int64_t n_rays,
                            uint8_t* flags, hipStream_t s) {
-  const PmGrid g{n, origin[0], origin[1], origin[2], h, periodic};
   const dim3 grid(blocks_for(n_rays, 256)), block(256);
   switch (n_int) {
     case 1:
-      hipLaunchKernelGGL(pm_trace_kernel<1>, grid, block, 0, s, c, g, fields, nodes, step_begin, step_end, rays,
-                         n_rays, flags);
+      hipLaunchKernelGGL(pm_trace_kernel<1>, grid, block, 0, s, c, grids, step_grid, nodes, step_begin, step_end,
+                         rays, n_rays, flags);
       break;
     case 2:
-      hipLaunchKernelGGL(pm_trace_kernel<2>, grid, block, 0, s, c, g, fields, nodes, step_begin, step_end, rays,
-                         n_rays, flags);
+      hipLaunchKernelGGL(pm_trace_kernel<2>, grid, block, 0, s, c, grids, step_grid, nodes, step_begin, step_end,
+                         rays, n_rays, flags);
       break;
     case 3:
-      hipLaunchKernelGGL(pm_trace_kernel<3>, grid, block, 0, s, c, g, fields, nodes, step_begin, step_end, rays,
-                         n_rays, flags);
+      hipLaunchKernelGGL(pm_trace_kernel<3>, grid, block, 0, s, c, grids, step_grid, nodes, step_begin, step_end,
+                         rays, n_rays, flags);
       break;
     default:
-      hipLaunchKernelGGL(pm_trace_kernel<4>, grid, block, 0, s, c, g, fields, nodes, step_begin, step_end, rays,
-                         n_rays, flags);
+      hipLaunchKernelGGL(pm_trace_kernel<4>, grid, block, 0, s, c, grids, step_grid, nodes, step_begin, step_end,
+                         rays, n_rays, flags);
       break;
   }
   return hipGetLastError();

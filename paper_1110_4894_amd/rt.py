@@ -99,7 +99,7 @@ def load(path: str = LIB_PATH):
         "rt_pm_workspace_bytes": (st, [p, p]),
         "rt_pm_build": (st, [p, p, p, p, C.c_size_t, p]),
         "rt_pm_eval": (st, [p, p, i32, i64, p, p, p, p]),
-        "rt_trace_pm": (st, [p, d, p, p, i32, i32, p, i32, i32, i64, p, p, p]),
+        "rt_trace_pm": (st, [p, d, i32, p, p, i32, i32, p, p, i32, i32, i64, p, p, p]),
         "rt_trace_pm_lambda": (st, [p, d, p, p, i32, d, i32, i64, p, p, p, p]),
     }
     for name, (res, args) in sigs.items():
@@ -300,12 +300,19 @@ def rt_pm_eval(grid: rt_pm_grid, fields, n_int: int, n: int, points, phi, grad, 
                              _stream(stream)))
 
 
-def rt_trace_pm(cosmo, z_source: float, grid: rt_pm_grid, fields, n_int: int, z_nodes, step_begin: int,
-                step_end: int, n_bundles: int, rays, ray_flags=None, stream=None):
+def rt_trace_pm(cosmo, z_source: float, grids, fields, n_int: int, z_nodes, step_begin: int, step_end: int,
+                n_bundles: int, rays, ray_flags=None, step_grid=None, stream=None):
+    """grids: one rt_pm_grid or a list; fields: the matching built field tensor(s)."""
+    if isinstance(grids, rt_pm_grid):
+        grids, fields = [grids], [fields]
+    garr = (rt_pm_grid * len(grids))(*grids)
+    farr = (C.c_void_p * len(fields))(*[_dptr(f) for f in fields])
     nodes = np.ascontiguousarray(z_nodes, dtype=np.float64)
-    _check(load().rt_trace_pm(C.byref(cosmo), float(z_source), C.byref(grid), _dptr(fields), int(n_int),
-                              int(nodes.size - 1), nodes.ctypes.data, int(step_begin), int(step_end), int(n_bundles),
-                              _dptr(rays), _dptr(ray_flags), _stream(stream)))
+    sg = None if step_grid is None else np.ascontiguousarray(step_grid, dtype=np.int32)
+    _check(load().rt_trace_pm(C.byref(cosmo), float(z_source), len(grids), C.addressof(garr), C.addressof(farr),
+                              int(n_int), int(nodes.size - 1), nodes.ctypes.data,
+                              None if sg is None else sg.ctypes.data, int(step_begin), int(step_end),
+                              int(n_bundles), _dptr(rays), _dptr(ray_flags), _stream(stream)))
 
 
 def rt_trace_pm_lambda(cosmo, z_source: float, grid: rt_pm_grid, fields, n_int: int, f_rk: float, max_steps: int,

@@ -149,6 +149,9 @@ def test_pm_argument_errors(lib):
     chi_s = rt.rt_comoving_distance(c, 0.5)
     nodes = rt.rt_make_schedule(chi_s, 0.0, chi_s, 10, 1.0)
     assert _status(rt.rt_trace_pm, c, 0.5, g, fake, 2, nodes[::-1].copy(), 0, 10, 2, fake) == -4
+    assert _status(rt.rt_trace_pm, c, 0.5, [g, g], [fake, fake], 2, nodes, 0, 10, 2, fake, None,
+                   np.full(10, 2, np.int32)) == -1
+    assert "step_grid" in rt.rt_last_error()
     assert _status(rt.rt_trace_pm, c, 0.5, g, fake, 2, nodes * 0.9, 0, 10, 2, fake) == -4
     around = rt.pm_grid(32, (-1.0, -1.0, -1.0), 0.0625)
     assert _status(rt.rt_trace_pm, c, 0.5, around, fake, 2, nodes, 0, 10, 2, fake) == -1
@@ -165,5 +168,4 @@ def test_pm_argument_errors(lib):
     bad = rt.pm_grid(32, (0, 0, 0), 0.1)
     bad.periodic = 2
     assert _status(rt.rt_pm_workspace_bytes, bad) == -1
-    assert _status(rt.rt_trace_pm, c, 0.5, pg, fake, 2, nodes, 0, 10, 2, fake) == -7
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, pg, fake, 2, 0.5, 100, 2, fake) == -7
