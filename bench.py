@@ -59,8 +59,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="nfw", choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm"])
-    p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid (nfw_pm)")
+    p.add_argument("--workload", default="nfw",
+                   choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm", "box18_pm", "box20_pm"])
+    p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid(s)")
+    p.add_argument("--pm-compare-stride", type=int, default=0,
+                   help="box*_pm: trace every k-th bundle of the grid with the direct sum too (0: 9 for box18, none "
+                        "for box20)")
     p.add_argument("--pm-nint", type=int, default=2, help="App. B interpolation nodes on each side (nfw_pm)")
     p.add_argument("--pm-frk", type=float, default=0.0,
                    help="nfw_pm: > 0 integrates in the affine parameter with the step f_RK h / kz_0 (eq. RKstepsize) "
@@ -121,8 +125,8 @@ def build_workload(a):
     if a.workload == "point":
         return workloads.schwarzschild(), ("point lens 1e12 Msun at z_l 0.25, z_s 0.5, 32x32 bundles at "
                                            "0.5-10 theta_E, r_b 1e-3 arcsec, 1000 fine RK4 steps")
-    if a.workload in ("box18", "box20"):
-        n, side = (18, 128) if a.workload == "box18" else (20, 512)
+    if a.workload in ("box18", "box20", "box18_pm", "box20_pm"):
+        n, side = (18, 128) if a.workload.startswith("box18") else (20, 512)
         return workloads.box(n_part_log2=n, n_side=side), (
             "Zel'dovich box 2^%d particles, 100 Mpc/h, 14 replicas to z_s 0.5, %dx%d bundles over 1 deg, "
             "r_b 0.1 arcsec, 2000 RK4 steps, softening 50 kpc/h" % (n, side, side))
@@ -173,6 +177,8 @@ def main():
     prec = rt.RT_FP64 if a.precision == "fp64" else rt.RT_FP32_KAHAN
     if a.workload == "nfw_pm":
         return bench_pm(a, torch, rt, workloads, GpuRun, dev)
+    if a.workload in ("box18_pm", "box20_pm"):
+        return bench_box_pm(a, torch, rt, workloads, GpuRun, dev)
 
     t_setup = time.time()
     w, desc = build_workload(a)
@@ -428,6 +434,93 @@ def bench_pm(a, torch, rt, workloads, GpuRun, dev):
                                   "n": int(rel.size), "impact_over_rs_p50_all": float(np.median(r_rs)),
                                   "impact_over_rs_max_beyond_3pct": float(r_rs[bad].max()) if bad.any() else None,
                                   "impact_over_rs_min_within_3pct": float(r_rs[~bad].min()) if (~bad).any() else None}
+    print(json.dumps(result), flush=True)
+
+
+def bench_box_pm(a, torch, rt, workloads, GpuRun, dev):
+    """The whole bundle grid of a Zel'dovich box light cone through 14 periodic particle-mesh
+    grids, one per replica (Sec. 3.3, App. B): build the grids once, then time bundles + trace +
+    magnification + muPDF of the full grid per step; untimed, every k-th bundle is also traced
+    with the direct sum for the mu comparison."""
+    w, desc = build_workload(a)
+    f = w.fields[0]
+    L = f.replica_box
+    n = a.pm_n
+    g = GpuRun(w)
+    grids, fields = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ws = None
+    build_ms = 0.0
+    for r, s in enumerate(f.sets):
+        grid = rt.pm_grid(n, (-0.5 * L, -0.5 * L, r * L), L / n, periodic=True)
+        nb_ws = rt.rt_pm_workspace_bytes(grid)
+        if ws is None:
+            ws = torch.empty(nb_ws, dtype=torch.uint8, device=dev)
+        fl = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+        pset = rt.make_particle_set(g.fields[0]["sets"][r]["xyzm"], softening=s.softening)
+        e0.record()
+        rt.rt_pm_build(pset, grid, fl, ws, nb_ws)
+        e1.record()
+        torch.cuda.synchronize()
+        build_ms += e0.elapsed_time(e1)
+        grids.append(grid)
+        fields.append(fl)
+    del ws
+    print("%d periodic grids of %d^3 (h = %.3f Mpc) built in %.1f ms" % (len(grids), n, L / n, build_ms),
+          file=sys.stderr, flush=True)
+    nodes = g.fields[0]["z_nodes"]
+    step_grid = g.fields[0]["step_set"]
+    nb = g.n_bundles
+    pdf = torch.empty(200, dtype=torch.float64, device=dev)
+    mom = torch.empty(6, dtype=torch.float64, device=dev)
+
+    def one_step():
+        g.build_bundles()
+        rt.rt_trace_pm(g.cosmo, w.z_source, grids, fields, a.pm_nint, nodes, 0, len(nodes) - 1, nb, g.rays, g.flags,
+                       step_grid=step_grid)
+        g.magnification()
+        rt.rt_mu_histogram(nb, g.mu, 200, -0.1, 0.3, pdf, mom)
+
+    for i in range(a.warmup):
+        one_step()
+        torch.cuda.synchronize()
+        print("warmup step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        one_step()
+        torch.cuda.synchronize()
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    mu_pm = g.mu.cpu().numpy()
+    m = mom.cpu().numpy()
+    ray_stages = 9.0 * nb * 4 * (len(nodes) - 1)
+    result = {
+        "metric": "bundles/s through the particle-mesh field", "value": nb * a.steps / elapsed, "unit": "bundles/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc + "; every bundle of the grid, each replica on a periodic %d^3 particle-mesh grid "
+                               "(h = %.3f Mpc), App. B with n_int = %d, RK4 over the z nodes; one step = %d bundles"
+                               % (n, L / n, a.pm_nint, nb),
+                   "name": a.workload, "grid": n, "h_mpc": L / n, "n_int": a.pm_nint, "replicas": len(grids),
+                   "rk4_steps": len(nodes) - 1},
+        "ray_stages_per_s": ray_stages * a.steps / elapsed,
+        "pm_build_ms_all_replicas": build_ms,
+        "mu_pdf_moments": {"mean_w": float(m[1]), "sigma_w": float(m[2]), "n_nonpositive": int(m[3]),
+                           "below": int(m[4]), "above": int(m[5])},
+        "flagged_rays": int(np.count_nonzero(g.flags.cpu().numpy())),
+    }
+    stride = a.pm_compare_stride or (9 if a.workload == "box18_pm" else 0)
+    if stride:
+        sub = workloads.subsample(w, stride)
+        gd = GpuRun(sub)
+        gd.run(rt.RT_FP32_KAHAN)
+        md = gd.mu.cpu().numpy()
+        rel = np.abs(mu_pm[::stride][: md.size] / md - 1)
+        result["mu_vs_direct_sum"] = {"p50": float(np.median(rel)), "p90": float(np.percentile(rel, 90)),
+                                      "max": float(rel.max()), "frac_within_1pct": float(np.mean(rel < 0.01)),
+                                      "n": int(rel.size), "direct_mean_mu": float(md.mean()),
+                                      "pm_mean_mu_same_bundles": float(mu_pm[::stride][: md.size].mean())}
     print(json.dumps(result), flush=True)
 
 

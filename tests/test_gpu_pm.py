@@ -258,3 +258,52 @@ def test_periodic_pm_eval_matches_oracle_on_the_same_grids(n_int):
                      for i in range(pts.shape[1])]).T
     for q in range(4):
         assert np.max(np.abs(got[q] - want[q])) <= 1e-12 * np.abs(F[q]).max(), q
+
+
+def test_box_light_cone_through_periodic_replica_grids_matches_oracle():
+    """A 2^12-particle Zel'dovich box in 14 replicas, each on its own periodic 16^3 grid; the
+    replica of each step chosen by the step's midpoint as for the direct sum; 200 uniform steps;
+    bundles built from the direct-sum field (potential at the observer from replica 0)."""
+    from paper_1110_4894_amd.runner import GpuRun
+    from tests.oracle_run import oracle_fields
+    w = wl.box(n_part_log2=12, n_side=4, n_steps=200)
+    w = wl.subsample(w, 5, 1, max_bundles=2)
+    f = w.fields[0]
+    L = f.replica_box
+    n, n_int = 16, 2
+    g = GpuRun(w)
+    dev = torch.device("cuda")
+    grids, fields, ofields = [], [], []
+    for r, s in enumerate(f.sets):
+        origin = np.array([-0.5 * L, -0.5 * L, r * L])
+        grid = rt.pm_grid(n, origin, L / n, periodic=True)
+        nb = rt.rt_pm_workspace_bytes(grid)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        fl = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+        pset = rt.make_particle_set(g.fields[0]["sets"][r]["xyzm"], softening=s.softening)
+        rt.rt_pm_build(pset, grid, fl, ws, nb)
+        grids.append(grid)
+        fields.append(fl)
+        F = opm.periodic_field(opm.cic_deposit_periodic(s.xyz, s.m, origin, L / n, n), L / n)
+        ofields.append((F, opm.spline_y2_periodic(F, L / n), origin, L / n, True))
+    nodes = g.fields[0]["z_nodes"]
+    step_grid = g.fields[0]["step_set"]
+    g.build_bundles()
+    rt.rt_trace_pm(g.cosmo, w.z_source, grids, fields, n_int, nodes, 0, len(nodes) - 1, g.n_bundles, g.rays,
+                   g.flags, step_grid=step_grid)
+    g.magnification()
+    torch.cuda.synchronize()
+    g_rays, g_mu = g.rays.cpu().numpy(), g.mu.cpu().numpy()
+    assert not g.flags.cpu().numpy().any()
+    c, chi_s, ofl, theta = oracle_fields(w)
+    assert np.allclose(ofl[0].z_nodes, nodes, rtol=1e-13, atol=0)
+    assert np.array_equal(ofl[0].step_set, step_grid)
+    orays = orc.build_bundles(c, ofl, theta, w.bundle_radius)
+    print("    [pm] oracle light cone through %d replica grids, %d rays" % (len(ofields), orays.shape[1]), flush=True)
+    orays, oflags = opm.trace_pm_steps(c, ofl[0].z_nodes, orays, ofields, ofl[0].step_set, n_int)
+    omu, _ = orc.magnification(chi_s, orays, w.bundle_radius)
+    assert not oflags.any()
+    assert np.max(np.abs(g_mu / omu - 1)) < 1e-7
+    th = np.repeat(theta, 9, axis=1)
+    defl = np.hypot(orays[1] - th[0] * chi_s, orays[2] - th[1] * chi_s)
+    assert np.all(np.hypot(g_rays[1] - orays[1], g_rays[2] - orays[2]) <= 1e-7 * defl + 1e-12)
