@@ -17,11 +17,15 @@ Untimed: the bundles of the first timed batch are also traced in FP64 on the
 GPU, to give the mixed-vs-FP64 mu error and the FP64 throughput; the CPU oracle
 is timed on two bundles of the batch (full schedule, all particles).
 
-Other workloads (--workload), for the per-workload table of the design notes:
+Other workloads (--workload), for the per-workload tables of the design notes:
 point (32 x 32 bundles around a 1e12 Msun point lens, 1225 steps), box18 /
 box20 (Zel'dovich boxes of 2^18 / 2^20 particles in 14 replicas, 0.1 arcsec
 bundles, 2000 steps; one step = one band of --band bundles), batched (64 uneven
-fields traced in one launch, --side x --side bundles per field).
+fields traced in one launch, --side x --side bundles per field); and the
+particle-mesh field: nfw_pm (the NFW band through a --pm-n^3 mesh, RK4 in z or,
+with --pm-frk, in the affine parameter), box18_pm / box20_pm (every bundle of the
+box grid through one periodic mesh per replica), pm_study (minimum reliable
+radius of the point lens against mesh resolution and n_int).
 
 Prints one JSON line.
 """
@@ -50,7 +54,8 @@ FLOP_PER_INTERACTION = 20.0
 # (kernel_source_sha; the first two entries hashed rt_kernels.hip alone).
 MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0},
                     "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0},
-                    "d9ecd4450456f251": {"read": 791484190955.2822, "write": 309593703488.0,
+                    "d9ecd4450456f251": {"read": 791484190955.2822, "write": 309593703488.0},
+                    "4447ca04a41774c8": {"read": 527069855930.1256, "write": 65751117760.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 
@@ -60,7 +65,8 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="nfw",
-                   choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm", "box18_pm", "box20_pm"])
+                   choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm", "box18_pm", "box20_pm",
+                            "pm_study"])
     p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid(s)")
     p.add_argument("--pm-compare-stride", type=int, default=0,
                    help="box*_pm: trace every k-th bundle of the grid with the direct sum too (0: 9 for box18, none "
@@ -179,6 +185,8 @@ def main():
         return bench_pm(a, torch, rt, workloads, GpuRun, dev)
     if a.workload in ("box18_pm", "box20_pm"):
         return bench_box_pm(a, torch, rt, workloads, GpuRun, dev)
+    if a.workload == "pm_study":
+        return bench_pm_study(a, torch, rt, workloads, dev)
 
     t_setup = time.time()
     w, desc = build_workload(a)
@@ -522,6 +530,60 @@ def bench_box_pm(a, torch, rt, workloads, GpuRun, dev):
                                       "n": int(rel.size), "direct_mean_mu": float(md.mean()),
                                       "pm_mean_mu_same_bundles": float(mu_pm[::stride][: md.size].mean())}
     print(json.dumps(result), flush=True)
+
+
+def bench_pm_study(a, torch, rt, workloads, dev):
+    """The mesh parameter study of Sec. 4.1 (Fig. 1) on the point lens: for meshes of several
+    resolutions and n_int, the minimum reliable radius (MRR), the smallest x = theta / theta_E
+    beyond which every bundle's mu is within 3% of the Schwarzschild value (App. C)."""
+    w = workloads.schwarzschild()
+    f = w.fields[0]
+    c = rt.cosmology(w.cosmology.omega_m, w.cosmology.omega_lambda, w.cosmology.h)
+    chi_s = rt.rt_comoving_distance(c, w.z_source)
+    chi_l, th_e = f.meta["chi_l"], f.meta["theta_E"]
+    x = f.meta["x"]
+    want = 1.0 / (1.0 - x ** -4)
+    half = 25.0 * th_e * chi_l                      # mesh half-width: 2.5 times the outermost bundle
+    nb = f.n_bundles
+    theta = torch.from_numpy(np.ascontiguousarray(f.theta)).to(dev)
+    xyzm = torch.from_numpy(np.ascontiguousarray(np.concatenate([f.sets[0].xyz.T, f.sets[0].m[None]], 0))).to(dev)
+    pset = rt.make_particle_set(xyzm)
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    rows = []
+    for n in (64, 128, 256):
+        h = 2 * half / (n - 1)
+        grid = rt.pm_grid(n, (-half, -half, chi_l - half), h)
+        nbytes = rt.rt_pm_workspace_bytes(grid)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        fields = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+        rt.rt_pm_build(pset, grid, fields, ws, nbytes)
+        del ws
+        nodes = rt.rt_make_schedule(chi_s, chi_l - half, chi_l + half, 2 * (n - 1), 1.1)
+        empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(len(nodes) - 1, -1, np.int32),
+                                "bundle_offset": 0, "n_bundles": nb}])
+        for n_int in (1, 2, 3):
+            rt.rt_build_bundles(c, empty, nb, theta, w.bundle_radius, rays)
+            flags.zero_()
+            t0 = time.perf_counter()
+            rt.rt_trace_pm(c, w.z_source, grid, fields, n_int, nodes, 0, len(nodes) - 1, nb, rays, flags)
+            rt.rt_magnification(c, w.z_source, nb, w.bundle_radius, rays, mu, None)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            err = np.abs(mu.cpu().numpy() / want - 1)
+            bad = x[err >= 0.03]
+            mrr = float(bad.max()) if bad.size else float(x.min())
+            rows.append({"n": n, "h_kpc": h * 1e3, "h_over_r_E": h / (th_e * chi_l), "n_int": n_int,
+                         "mrr_theta_E": mrr, "median_err_x_ge_2": float(np.median(err[x >= 2])), "trace_ms": ms})
+            print("n %d n_int %d: MRR %.2f theta_E" % (n, n_int, mrr), file=sys.stderr, flush=True)
+        del fields
+    print(json.dumps({"metric": "minimum reliable radius of the mesh field (3% of the Schwarzschild mu)",
+                      "unit": "theta_E", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "point lens 1e12 Msun at z_l 0.25, z_s 0.5, 32x32 bundles at 0.5-10 "
+                                             "theta_E; isolated mesh of half-width 25 theta_E chi_l around it",
+                                 "name": "pm_study"},
+                      "rows": rows}), flush=True)
 
 
 if __name__ == "__main__":

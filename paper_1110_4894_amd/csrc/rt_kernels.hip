@@ -229,8 +229,11 @@ template <bool F64, int T, int WPR>
 struct FieldEval {
   using Tile = typename TileSpace<F64, T>::Elem;
 
+  // red_in_tiles: red lives in the LDS tiles of the workgroup, so every wavefront must have
+  // finished its pair loop before the partial sums are written.
   __device__ static void eval(const DevCosmo& c, const DevSet& s, Tile* tile, double* red, int q, int lane, double x,
-                              double y, double z, double& phi, double& gx, double& gy, double& gz) {
+                              double y, double z, double& phi, double& gx, double& gy, double& gz,
+                              bool red_in_tiles = false) {
     double S0, Sx, Sy, Sz;
     if constexpr (F64) {
       sum_fp64<T, WPR>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
@@ -252,6 +255,7 @@ struct FieldEval {
     }
     if constexpr (WPR > 1) {
       // red: [WPR][4][64] for this group
+      if (red_in_tiles) __syncthreads();
       red[(q * 4 + 0) * 64 + lane] = S0;
       red[(q * 4 + 1) * 64 + lane] = Sx;
       red[(q * 4 + 2) * 64 + lane] = Sy;
@@ -282,6 +286,22 @@ struct FieldEval {
   }
 };
 
+__device__ __forceinline__ void store_state(double* st, int lane, int at, const State& v) {
+  st[(at + 0) * 64 + lane] = v.t;
+  st[(at + 1) * 64 + lane] = v.x;
+  st[(at + 2) * 64 + lane] = v.y;
+  st[(at + 3) * 64 + lane] = v.kt;
+  st[(at + 4) * 64 + lane] = v.kx;
+  st[(at + 5) * 64 + lane] = v.ky;
+  st[(at + 6) * 64 + lane] = v.kz;
+}
+
+__device__ __forceinline__ State load_state(const double* st, int lane, int at) {
+  return State{st[(at + 0) * 64 + lane], st[(at + 1) * 64 + lane], st[(at + 2) * 64 + lane],
+               st[(at + 3) * 64 + lane], st[(at + 4) * 64 + lane], st[(at + 5) * 64 + lane],
+               st[(at + 6) * 64 + lane]};
+}
+
 // ---------------------------------------------------------------------------
 // The persistent trace kernel.
 // NW wavefronts per workgroup; WPR of them share 63 rays (7 bundles) and split
@@ -294,13 +314,25 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   constexpr int NG = NW / WPR;
   using FE = FieldEval<F64, T, WPR>;
   using Tile = typename FE::Tile;
+  // When the WPR wavefronts of a group share rays, one copy of the group's FP64
+  // RK4 state (Y, the stage input and the accumulator: 21 values per ray) waits
+  // in LDS while the field is summed, instead of 128-VGPR wavefronts spilling
+  // their identical copies to scratch.  The reduction buffer then shares the
+  // tiles' LDS, so that the state fits beside them at two workgroups per CU.
+  constexpr int kStateWords = 21 * 64;
+  constexpr int kTileBytes = NW * TileSpace<F64, T>::kElems * (int)sizeof(Tile);
+  constexpr bool kLdsState = WPR >= 2 && kTileBytes + NG * kStateWords * 8 <= 80 * 1024 &&
+                             kTileBytes >= NG * WPR * 4 * 64 * 8;
   __shared__ Tile tiles[NW][TileSpace<F64, T>::kElems];
-  __shared__ double red[NG][WPR > 1 ? WPR * 4 * 64 : 1];
+  __shared__ double red_own[NG][(WPR > 1 && !kLdsState) ? WPR * 4 * 64 : 1];
+  __shared__ double state_lds[kLdsState ? NG : 1][kLdsState ? kStateWords : 1];
   __shared__ int s_item;
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = wave / WPR, q = wave % WPR;
   const DevCosmo& cz = P.cosmo;
+  double* red = kLdsState ? reinterpret_cast<double*>(&tiles[0][0]) + g * (WPR * 4 * 64) : &red_own[g][0];
+  double* st = &state_lds[kLdsState ? g : 0][0];
 
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(P.queue, 1);
@@ -328,17 +360,32 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
       const double Z0 = P.nodes[f.node_off + s], Z1 = P.nodes[f.node_off + s + 1];
       const double h = Z1 - Z0, hh = 0.5 * h;
       const int S = P.step_set[f.step_off + s];
-      State acc, Ys, k;
+      State acc{}, Ys{}, k;
       double a;
 #pragma unroll 1
       for (int stage = 0; stage < 4; ++stage) {
-        const State& Yin = (stage == 0) ? Y : Ys;
+        const double xin = (stage == 0) ? Y.x : Ys.x, yin = (stage == 0) ? Y.y : Ys.y;
         const double zs = (stage == 0) ? Z0 : ((stage == 3) ? Z1 : Z0 + hh);
+        if constexpr (kLdsState) {
+          if (q == 0) {
+            store_state(st, lane, 0, Y);
+            store_state(st, lane, 7, acc);
+            store_state(st, lane, 14, Ys);
+          }
+        }
         double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         if (S >= 0) {
           const DevSet& set = P.sets[f.set_off + S];
-          FE::eval(cz, set, tiles[wave], red[g], q, lane, Yin.x, Yin.y, zs, phi, gx, gy, gz);
+          FE::eval(cz, set, tiles[wave], red, q, lane, xin, yin, zs, phi, gx, gy, gz, kLdsState);
         }
+        if constexpr (kLdsState) {
+          if (S < 0) __syncthreads();   // the field sum's barriers order the stores otherwise
+          Y = load_state(st, lane, 0);
+          acc = load_state(st, lane, 7);
+          Ys = load_state(st, lane, 14);
+          __syncthreads();              // every wavefront has its copy before the next stores
+        }
+        const State& Yin = (stage == 0) ? Y : Ys;
         k = rhs(cz, Yin, phi, gx, gy, gz, a);
         if (stage == 0) {
           if (fabs(phi) / a > 1e-2) flag |= 4;
