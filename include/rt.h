@@ -283,6 +283,10 @@ rt_status rt_enable_timing(int32_t on);
 /* Information on the last rt_trace of the calling process; waits for its kernel if timed. */
 rt_status rt_last_trace_info(rt_trace_info* info);
 
+/* Wait for all work enqueued on `stream` and report what it left: RT_OK, or RT_ERR_DEVICE with
+ * the HIP error of earlier asynchronous work (a fault in a kernel, for instance). */
+rt_status rt_sync(hipStream_t stream);
+
 /* Message for the last non-OK status of the calling thread ("" if none). */
 const char* rt_last_error(void);
 

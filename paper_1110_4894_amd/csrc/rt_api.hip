@@ -491,6 +491,12 @@ int choose_plan(bool fp64, const Workload& w, const DeviceInfo& di) {
 // ============================================================================ C ABI
 extern "C" {
 
+rt_status rt_sync(hipStream_t stream) {
+  RT_HIP(hipStreamSynchronize(stream));
+  RT_HIP(hipGetLastError());
+  return RT_OK;
+}
+
 const char* rt_last_error(void) { return g_err.c_str(); }
 
 rt_status rt_comoving_distance(const rt_cosmology* cosmo, double z, double* chi_out) {

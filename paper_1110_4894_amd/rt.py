@@ -63,7 +63,7 @@ class rt_pm_grid(C.Structure):
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
            "rt_magnification", "rt_mu_histogram", "rt_shear_histogram", "rt_field_eval", "rt_plan_count", "rt_plan_describe",
            "rt_force_plan", "rt_set_grid_limit", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
-           "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda"]
+           "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda", "rt_sync"]
 
 _lib = None
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "rt_enable_timing": (st, [i32]),
         "rt_last_trace_info": (st, [p]),
         "rt_last_error": (C.c_char_p, []),
+        "rt_sync": (st, [p]),
         "rt_release_caches": (None, []),
         "rt_pm_workspace_bytes": (st, [p, p]),
         "rt_pm_build": (st, [p, p, p, p, C.c_size_t, p]),
@@ -270,6 +271,10 @@ def rt_last_trace_info() -> dict:
     info = rt_trace_info()
     _check(load().rt_last_trace_info(C.addressof(info)))
     return {k: getattr(info, k) for k, _ in rt_trace_info._fields_}
+
+
+def rt_sync(stream=None):
+    _check(load().rt_sync(_stream(stream)))
 
 
 def rt_last_error() -> str:
