@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -349,7 +350,10 @@ rt_status build_entry(TraceEntry* e, const DeviceInfo& di, const rt_cosmology& c
   std::vector<double> nodes;
   std::vector<int32_t> steps;
   std::vector<std::pair<double, WorkItem>> items;
-  std::map<std::pair<const double*, int64_t>, float4*> p32_of;
+  // One FP32 copy per particle array and frame: the frame origin depends on the
+  // background cuboid, so the key holds it too.
+  using ConvKey = std::tuple<const double*, int64_t, int32_t, std::array<double, 6>>;
+  std::map<ConvKey, std::pair<float4*, int32_t*>> p32_of;
   for (int f = 0; f < n_fields; ++f) {
     const rt_field& F = fields[f];
     DevField& d = hf[f];
@@ -375,16 +379,21 @@ rt_status build_entry(TraceEntry* e, const DeviceInfo& di, const rt_cosmology& c
       }
       ds.p32 = nullptr;
       if (!fp64 && s.n > 0) {
-        auto key = std::make_pair(s.xyzm, s.n);
+        std::array<double, 6> box{};
+        if (s.background) box = {s.lo[0], s.lo[1], s.lo[2], s.hi[0], s.hi[1], s.hi[2]};
+        const ConvKey key{s.xyzm, s.n, s.background, box};
         auto it = p32_of.find(key);
         if (it == p32_of.end()) {
           float4* p;
+          int32_t* eq;
           rt_status st = dev_alloc(e, &p, (size_t)s.n);
           if (st != RT_OK) return st;
-          it = p32_of.emplace(key, p).first;
+          if ((st = dev_alloc(e, &eq, 1)) != RT_OK) return st;
+          it = p32_of.emplace(key, std::make_pair(p, eq)).first;
           e->conv.push_back({(int32_t)hs.size(), s.xyzm, p, s.n});
         }
-        ds.p32 = it->second;
+        ds.p32 = it->second.first;
+        ds.equal_mass = it->second.second;
       }
       hs.push_back(ds);
     }
@@ -751,11 +760,15 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
     hs.hi[k] = set->hi[k];
   }
   const size_t p32_bytes = (!fp64 && set->n > 0) ? sizeof(float4) * (size_t)set->n : 0;
+  // scratch: DevSet, its equal-mass flag, then (256-byte aligned) the FP32 copy
+  const size_t flag_off = ((sizeof(DevSet) + 7) / 8) * 8;
+  const size_t p32_off = ((flag_off + sizeof(int32_t) + 255) / 256) * 256;
   void* scratch = nullptr;
-  RT_HIP(hipMallocAsync(&scratch, sizeof(DevSet) + p32_bytes + 256, stream));
+  RT_HIP(hipMallocAsync(&scratch, p32_off + p32_bytes, stream));
   DevSet* d_set = static_cast<DevSet*>(scratch);
-  float4* p32 = reinterpret_cast<float4*>(static_cast<char*>(scratch) + ((sizeof(DevSet) + 255) / 256) * 256);
+  float4* p32 = reinterpret_cast<float4*>(static_cast<char*>(scratch) + p32_off);
   hs.p32 = p32_bytes ? p32 : nullptr;
+  hs.equal_mass = p32_bytes ? reinterpret_cast<int32_t*>(static_cast<char*>(scratch) + flag_off) : nullptr;
   RT_HIP(hipMemcpyAsync(d_set, &hs, sizeof(DevSet), hipMemcpyHostToDevice, stream));
   RT_HIP(hipStreamSynchronize(stream));   // hs is a local
   RT_HIP(launch_prepare_sets(d_set, 1, stream));

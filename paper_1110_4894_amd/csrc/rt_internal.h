@@ -24,10 +24,12 @@ struct DevCosmo {
 struct DevSet {
   const double* p64;   // caller's [4][n] (x, y, z, m)
   float4* p32;         // library copy: (x - org, y - org, z - org, m) in FP32, [n]
+  int32_t* equal_mass; // with p32: 1 when every mass equals mass (set on the device), shared with p32
   int64_t n;
   double eps2;         // softening^2, FP64
   float eps2f;         // softening^2, FP32
   int32_t background;
+  double mass;         // the first particle's mass (filled on the device)
   double org[3];       // frame origin of p32 (filled on the device)
   double lo[3], hi[3]; // background cuboid
 };

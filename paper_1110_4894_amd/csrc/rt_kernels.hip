@@ -119,6 +119,78 @@ constexpr int kCopyStride = kTile32 + 1;  // float4 per bundle copy (+1 spreads 
 
 __device__ __forceinline__ int lane_segment(int lane) { return lane < kLanes ? lane / 9 : kSeg - 1; }
 
+// FP32 path, equal masses: the staged copies hold positions only, four
+// particles in three float4 (x0 y0 z0 x1 | y1 z1 x2 y2 | z2 x3 y3 z3), so the
+// pair loop issues three LDS reads per four particles instead of four (the
+// loop is bound by VALU issue and LDS returns together); the caller multiplies
+// the unit-mass sums by the common mass.
+constexpr int kPackedStride = 3 * kTile32 / 4 + 1;   // float4 per bundle copy
+static_assert(kPackedStride <= kCopyStride, "the packed copies fit in the general tile");
+
+template <int WPR>
+__device__ __forceinline__ void sum_fp32_equal(const DevSet& s, float4* tile, int q, int lane,
+                                               const float (&A)[kSeg][3], float rx, float ry, float rz, double& S0,
+                                               double& Sx, double& Sy, double& Sz) {
+  static_assert(kKahanChunk % 4 == 0 && kTile32 % kKahanChunk == 0, "packed groups of four");
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+  const int64_t n = s.n;
+  const float e2 = s.eps2f;
+  const int64_t n_chunks = (n + kTile32 - 1) / kTile32;
+  const float4* __restrict__ src = s.p32;
+  float* tf = reinterpret_cast<float*>(tile);
+  const float4* mine = tile + lane_segment(lane) * kPackedStride;
+  for (int64_t ch = q; ch < n_chunks; ch += WPR) {
+    const int64_t j = ch * kTile32 + lane;
+    // Padding past the end sits so far away that r^2 overflows to +inf, whose
+    // reciprocal square root is +0: it adds exactly nothing.
+    const float4 p = (j < n) ? src[j] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
+#pragma unroll
+    for (int b = 0; b < kSeg; ++b) {
+      float* d = tf + 4 * b * kPackedStride + 3 * lane;
+      d[0] = p.x - A[b][0];
+      d[1] = p.y - A[b][1];
+      d[2] = p.z - A[b][2];
+    }
+    wave_sync();
+#pragma unroll 1
+    for (int k0 = 0; k0 < kTile32; k0 += kKahanChunk) {
+      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+      for (int u = 0; u < kKahanChunk / 4; ++u) {
+        const float4* g = mine + 3 * (k0 / 4 + u);
+        const float4 P0 = g[0], P1 = g[1], P2 = g[2];
+        const float px[4] = {P0.x, P0.w, P1.z, P2.y};
+        const float py[4] = {P0.y, P1.x, P1.w, P2.z};
+        const float pz[4] = {P0.z, P1.y, P2.x, P2.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float ex = px[v] - rx, ey = py[v] - ry, ez = pz[v] - rz;
+          float r2 = fmaf(ex, ex, e2);
+          r2 = fmaf(ey, ey, r2);
+          r2 = fmaf(ez, ez, r2);
+          const float ri = __builtin_amdgcn_rsqf(r2);
+          p0 += ri;
+          const float r3 = ri * ri * ri;
+          p1 = fmaf(r3, ex, p1);
+          p2 = fmaf(r3, ey, p2);
+          p3 = fmaf(r3, ez, p3);
+        }
+      }
+      kahan_add(s0, c0, p0);
+      kahan_add(s1, c1, p1);
+      kahan_add(s2, c2, p2);
+      kahan_add(s3, c3, p3);
+    }
+    wave_sync();
+  }
+  const double m = s.mass;
+  S0 = m * ((double)s0 - (double)c0);
+  Sx = m * ((double)s1 - (double)c1);
+  Sy = m * ((double)s2 - (double)c2);
+  Sz = m * ((double)s3 - (double)c3);
+}
+
 // FP32 path.  Each tile of 64 particles is staged once per bundle of the
 // wavefront, as particle - anchor (7 copies); each lane then subtracts only its
 // ray's small offset from its anchor.  The anchor-relative part is rounded
@@ -251,7 +323,10 @@ struct FieldEval {
         A[b][2] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), 9 * b));
       }
       const float rx = (float)(X - (double)ax), ry = (float)(Yv - (double)ay), rz = (float)(Z - (double)az);
-      sum_fp32<WPR>(s, tile, q, lane, A, rx, ry, rz, S0, Sx, Sy, Sz);
+      if (s.equal_mass && *s.equal_mass)
+        sum_fp32_equal<WPR>(s, tile, q, lane, A, rx, ry, rz, S0, Sx, Sy, Sz);
+      else
+        sum_fp32<WPR>(s, tile, q, lane, A, rx, ry, rz, S0, Sx, Sy, Sz);
     }
     if constexpr (WPR > 1) {
       // red: [WPR][4][64] for this group
@@ -471,6 +546,8 @@ __global__ void prepare_sets_kernel(DevSet* sets, int32_t n_sets) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_sets) return;
   DevSet& s = sets[i];
+  s.mass = (s.n > 0) ? s.p64[3 * s.n] : 0.0;
+  if (s.equal_mass) *s.equal_mass = 1;   // cleared by the FP32 conversion at the first other mass
   if (s.background) {
     for (int d = 0; d < 3; ++d) s.org[d] = 0.5 * (s.lo[d] + s.hi[d]);
   } else if (s.n > 0) {
@@ -484,8 +561,9 @@ __global__ void convert_set_kernel(const DevSet* set, const double* p64, float4*
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const double ox = set->org[0], oy = set->org[1], oz = set->org[2];
-  p32[j] = make_float4((float)(p64[j] - ox), (float)(p64[n + j] - oy), (float)(p64[2 * n + j] - oz),
-                       (float)p64[3 * n + j]);
+  const double m = p64[3 * n + j];
+  p32[j] = make_float4((float)(p64[j] - ox), (float)(p64[n + j] - oy), (float)(p64[2 * n + j] - oz), (float)m);
+  if (!(m == p64[3 * n])) *set->equal_mass = 0;   // (a NaN mass also takes the general path)
 }
 
 // ---------------------------------------------------------------------------
