@@ -47,7 +47,26 @@ if ROOT not in sys.path:
 METRIC = "ray-particle interactions/s and bundles/s at μ err ≤1e-4 vs FP64 (mixed vs FP64)"
 PEAK_FP32 = 157.3      # TFLOP/s, MI355X FP32 vector (published)
 PEAK_FP64 = 78.6       # TFLOP/s, MI355X FP64 vector (published)
+# Algorithmic FLOP per ray-particle interaction: 3 sub, 3 FMA (6), rsqrt (1),
+# m x 1/r (1), 1 add, 2 mul, 3 FMA (6) = 20; 19 for a set of equal masses, whose
+# common mass multiplies the finished sums instead.
 FLOP_PER_INTERACTION = 20.0
+FLOP_PER_INTERACTION_EQUAL_MASS = 19.0
+
+
+def flop_per_interaction(g) -> float:
+    """Interaction-weighted algorithmic FLOP per interaction of a GpuRun's fields."""
+    tot = eq = 0.0
+    for f, spec in zip(g.fields, g.w.fields):
+        equal = [bool(np.all(s.m == s.m[0])) for s in spec.sets]
+        ss = np.asarray(f["step_set"])
+        for j, s in enumerate(spec.sets):
+            n = float(len(s.m)) * f["n_bundles"] * np.count_nonzero(ss == j)
+            tot += n
+            eq += n if equal[j] else 0.0
+    if tot == 0.0:
+        return FLOP_PER_INTERACTION
+    return FLOP_PER_INTERACTION - (FLOP_PER_INTERACTION - FLOP_PER_INTERACTION_EQUAL_MASS) * eq / tot
 # HBM bytes per launch of the FP32 trace kernel on the default workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and
 # 1.0), keyed by the sha256 prefix of the kernel sources they were taken with
@@ -55,11 +74,11 @@ FLOP_PER_INTERACTION = 20.0
 MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0},
                     "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0},
                     "d9ecd4450456f251": {"read": 791484190955.2822, "write": 309593703488.0},
-                    "4447ca04a41774c8": {"read": 527069855930.1256, "write": 65751117760.0,
-                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"},
+                    "4447ca04a41774c8": {"read": 527069855930.1256, "write": 65751117760.0},
                     # changes only the FP64 instantiations: trace_kernel<false, 8, 8, 64> compiles to the
                     # same instructions (checked by diffing the gfx950 assembly)
-                    "799090d3d3da2c72": {"read": 527069855930.1256, "write": 65751117760.0,
+                    "799090d3d3da2c72": {"read": 527069855930.1256, "write": 65751117760.0},
+                    "ae59e4cd8fd79606": {"read": 438975467239.04016, "write": 28242255520.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 
@@ -248,7 +267,8 @@ def main():
     elapsed = t1 - t0
     value = inter_per_step * a.steps / elapsed
     k_ms = float(np.mean(kernel_ms))
-    achieved = FLOP_PER_INTERACTION * inter_per_step / (k_ms * 1e-3) / 1e12
+    flop = flop_per_interaction(g)
+    achieved = flop * inter_per_step / (k_ms * 1e-3) / 1e12
     peak = PEAK_FP64 if prec == rt.RT_FP64 else PEAK_FP32
     prec_name = "fp64" if prec == rt.RT_FP64 else "fp32-kahan field, fp64 integration"
     result = {
@@ -267,7 +287,7 @@ def main():
                      "frac": achieved / peak, "traffic": traffic_bytes(a),
                      "traffic_unit": "HBM bytes per launch (read + write)",
                      "kernel": "trace_kernel (%s)" % ("fp64" if prec == rt.RT_FP64 else "fp32"),
-                     "kernel_ms": k_ms, "flop_per_interaction": FLOP_PER_INTERACTION},
+                     "kernel_ms": k_ms, "flop_per_interaction": flop},
     }
 
     # ---------------------------------------------------------------- FP64 reference on the first batch
@@ -304,8 +324,8 @@ def main():
                                       "max_abs_mpc": float(dx.max())}
         rate64 = gs.interactions() / (info["kernel_ms"] * 1e-3)
         result["fp64"] = {"interactions_per_s": rate64, "bundles": int(m64.size), "kernel_ms": info["kernel_ms"],
-                          "tflops": FLOP_PER_INTERACTION * rate64 / 1e12,
-                          "frac_of_fp64_peak": FLOP_PER_INTERACTION * rate64 / 1e12 / PEAK_FP64,
+                          "tflops": flop * rate64 / 1e12,
+                          "frac_of_fp64_peak": flop * rate64 / 1e12 / PEAK_FP64,
                           "mixed_speedup": (inter_per_step / (k_ms * 1e-3)) / rate64}
         print("fp64 reference: %s" % json.dumps(result["mu_err_vs_fp64"]), file=sys.stderr, flush=True)
 
