@@ -34,7 +34,6 @@ namespace rt {
 
 namespace {
 
-constexpr int kKahanChunk = 64;     // particles summed plainly before a Kahan update
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -127,11 +126,35 @@ __device__ __forceinline__ int lane_segment(int lane) { return lane < kLanes ? l
 constexpr int kPackedStride = 3 * kTile32 / 4 + 1;   // float4 per bundle copy
 static_assert(kPackedStride <= kCopyStride, "the packed copies fit in the general tile");
 
+// Four packed particles (three float4) against the lane's ray, unit masses.
+__device__ __forceinline__ void pairs_equal4(const float4* g, float rx, float ry, float rz, float e2, float& p0,
+                                             float& p1, float& p2, float& p3) {
+  const float4 P0 = g[0], P1 = g[1], P2 = g[2];
+  const float px[4] = {P0.x, P0.w, P1.z, P2.y};
+  const float py[4] = {P0.y, P1.x, P1.w, P2.z};
+  const float pz[4] = {P0.z, P1.y, P2.x, P2.w};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float ex = px[v] - rx, ey = py[v] - ry, ez = pz[v] - rz;
+    float r2 = fmaf(ex, ex, e2);
+    r2 = fmaf(ey, ey, r2);
+    r2 = fmaf(ez, ez, r2);
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    p0 += ri;
+    const float r3 = ri * ri * ri;
+    p1 = fmaf(r3, ex, p1);
+    p2 = fmaf(r3, ey, p2);
+    p3 = fmaf(r3, ez, p3);
+  }
+}
+
+// Plain FP32 partial sums over one tile, added to the running sums with Kahan
+// compensation.  A set's last tile runs only over its particles (to the next
+// group of four), which is what a set of a few particles costs.
 template <int WPR>
 __device__ __forceinline__ void sum_fp32_equal(const DevSet& s, float4* tile, int q, int lane,
                                                const float (&A)[kSeg][3], float rx, float ry, float rz, double& S0,
                                                double& Sx, double& Sy, double& Sz) {
-  static_assert(kKahanChunk % 4 == 0 && kTile32 % kKahanChunk == 0, "packed groups of four");
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
   const int64_t n = s.n;
@@ -153,35 +176,20 @@ __device__ __forceinline__ void sum_fp32_equal(const DevSet& s, float4* tile, in
       d[2] = p.z - A[b][2];
     }
     wave_sync();
+    const int64_t left = n - ch * kTile32;
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+    if (left >= kTile32) {
+#pragma unroll
+      for (int u = 0; u < kTile32 / 4; ++u) pairs_equal4(mine + 3 * u, rx, ry, rz, e2, p0, p1, p2, p3);
+    } else {
+      const int groups = (int)((left + 3) / 4);
 #pragma unroll 1
-    for (int k0 = 0; k0 < kTile32; k0 += kKahanChunk) {
-      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-#pragma unroll
-      for (int u = 0; u < kKahanChunk / 4; ++u) {
-        const float4* g = mine + 3 * (k0 / 4 + u);
-        const float4 P0 = g[0], P1 = g[1], P2 = g[2];
-        const float px[4] = {P0.x, P0.w, P1.z, P2.y};
-        const float py[4] = {P0.y, P1.x, P1.w, P2.z};
-        const float pz[4] = {P0.z, P1.y, P2.x, P2.w};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float ex = px[v] - rx, ey = py[v] - ry, ez = pz[v] - rz;
-          float r2 = fmaf(ex, ex, e2);
-          r2 = fmaf(ey, ey, r2);
-          r2 = fmaf(ez, ez, r2);
-          const float ri = __builtin_amdgcn_rsqf(r2);
-          p0 += ri;
-          const float r3 = ri * ri * ri;
-          p1 = fmaf(r3, ex, p1);
-          p2 = fmaf(r3, ey, p2);
-          p3 = fmaf(r3, ez, p3);
-        }
-      }
-      kahan_add(s0, c0, p0);
-      kahan_add(s1, c1, p1);
-      kahan_add(s2, c2, p2);
-      kahan_add(s3, c3, p3);
+      for (int u = 0; u < groups; ++u) pairs_equal4(mine + 3 * u, rx, ry, rz, e2, p0, p1, p2, p3);
     }
+    kahan_add(s0, c0, p0);
+    kahan_add(s1, c1, p1);
+    kahan_add(s2, c2, p2);
+    kahan_add(s3, c3, p3);
     wave_sync();
   }
   const double m = s.mass;
@@ -189,6 +197,22 @@ __device__ __forceinline__ void sum_fp32_equal(const DevSet& s, float4* tile, in
   Sx = m * ((double)s1 - (double)c1);
   Sy = m * ((double)s2 - (double)c2);
   Sz = m * ((double)s3 - (double)c3);
+}
+
+// One (x, y, z, m) particle against the lane's ray.
+__device__ __forceinline__ void pair_general(const float4 c, float rx, float ry, float rz, float e2, float& p0,
+                                             float& p1, float& p2, float& p3) {
+  const float ex = c.x - rx, ey = c.y - ry, ez = c.z - rz;
+  float r2 = fmaf(ex, ex, e2);
+  r2 = fmaf(ey, ey, r2);
+  r2 = fmaf(ez, ez, r2);
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  const float mr = c.w * ri;
+  p0 += mr;
+  const float mr3 = mr * ri * ri;
+  p1 = fmaf(mr3, ex, p1);
+  p2 = fmaf(mr3, ey, p2);
+  p3 = fmaf(mr3, ez, p3);
 }
 
 // FP32 path.  Each tile of 64 particles is staged once per bundle of the
@@ -215,35 +239,40 @@ __device__ __forceinline__ void sum_fp32(const DevSet& s, float4* tile, int q, i
     for (int b = 0; b < kSeg; ++b)
       tile[b * kCopyStride + lane] = make_float4(p.x - A[b][0], p.y - A[b][1], p.z - A[b][2], p.w);
     wave_sync();
-#pragma unroll 1
-    for (int k0 = 0; k0 < kTile32; k0 += kKahanChunk) {
-      float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+    const int64_t left = n - ch * kTile32;
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+    if (left >= kTile32) {
 #pragma unroll
-      for (int u = 0; u < kKahanChunk; ++u) {
-        const float4 c = mine[k0 + u];
-        const float ex = c.x - rx, ey = c.y - ry, ez = c.z - rz;
-        float r2 = fmaf(ex, ex, e2);
-        r2 = fmaf(ey, ey, r2);
-        r2 = fmaf(ez, ez, r2);
-        const float ri = __builtin_amdgcn_rsqf(r2);
-        const float mr = c.w * ri;
-        p0 += mr;
-        const float mr3 = mr * ri * ri;
-        p1 = fmaf(mr3, ex, p1);
-        p2 = fmaf(mr3, ey, p2);
-        p3 = fmaf(mr3, ez, p3);
-      }
-      kahan_add(s0, c0, p0);
-      kahan_add(s1, c1, p1);
-      kahan_add(s2, c2, p2);
-      kahan_add(s3, c3, p3);
+      for (int u = 0; u < kTile32; ++u) pair_general(mine[u], rx, ry, rz, e2, p0, p1, p2, p3);
+    } else {
+#pragma unroll 1
+      for (int u = 0; u < (int)left; ++u) pair_general(mine[u], rx, ry, rz, e2, p0, p1, p2, p3);
     }
+    kahan_add(s0, c0, p0);
+    kahan_add(s1, c1, p1);
+    kahan_add(s2, c2, p2);
+    kahan_add(s3, c3, p3);
     wave_sync();
   }
   S0 = (double)s0 - (double)c0;
   Sx = (double)s1 - (double)c1;
   Sy = (double)s2 - (double)c2;
   Sz = (double)s3 - (double)c3;
+}
+
+__device__ __forceinline__ void pair_fp64(const double4 c, double x, double y, double z, double e2, double& a0,
+                                          double& a1, double& a2, double& a3) {
+  const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
+  double r2 = fma(ex, ex, e2);
+  r2 = fma(ey, ey, r2);
+  r2 = fma(ez, ez, r2);
+  const double ri = rsqrt_f64(r2);
+  const double mr = c.w * ri;
+  a0 += mr;
+  const double mr3 = mr * ri * ri;
+  a1 = fma(mr3, ex, a1);
+  a2 = fma(mr3, ey, a2);
+  a3 = fma(mr3, ez, a3);
 }
 
 // FP64 path: tiles of the caller's FP64 particles, broadcast to every lane.
@@ -264,20 +293,13 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, 
                         : make_double4(1e100, 1e100, 1e100, 0.0);
     }
     wave_sync();
+    const int64_t left = n - base;   // the set's last tile runs only over its particles
+    if (left >= T) {
 #pragma unroll 8
-    for (int k = 0; k < T; ++k) {
-      const double4 c = tile[k];
-      const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
-      double r2 = fma(ex, ex, e2);
-      r2 = fma(ey, ey, r2);
-      r2 = fma(ez, ez, r2);
-      const double ri = rsqrt_f64(r2);
-      const double mr = c.w * ri;
-      a0 += mr;
-      const double mr3 = mr * ri * ri;
-      a1 = fma(mr3, ex, a1);
-      a2 = fma(mr3, ey, a2);
-      a3 = fma(mr3, ez, a3);
+      for (int k = 0; k < T; ++k) pair_fp64(tile[k], x, y, z, e2, a0, a1, a2, a3);
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < (int)left; ++k) pair_fp64(tile[k], x, y, z, e2, a0, a1, a2, a3);
     }
     wave_sync();
   }
@@ -404,7 +426,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   __shared__ double state_lds[kLdsState ? NG : 1][kLdsState ? kStateWords : 1];
   __shared__ int s_item;
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform: keep it (and the tile loop counters) in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = wave / WPR, q = wave % WPR;
   const DevCosmo& cz = P.cosmo;
   double* red = kLdsState ? reinterpret_cast<double*>(&tiles[0][0]) + g * (WPR * 4 * 64) : &red_own[g][0];
@@ -516,7 +539,8 @@ __global__ __launch_bounds__(256) void field_eval_kernel(DevCosmo c, const DevSe
   using FE = FieldEval<F64, T, 1>;
   using Tile = typename FE::Tile;
   __shared__ Tile tiles[4][TileSpace<F64, T>::kElems];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform: keep it (and the tile loop counters) in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * kLanes;
   if (w0 >= n) return;   // whole wavefront idle
   int64_t i = w0 + (lane < kLanes ? lane : kLanes - 1);
