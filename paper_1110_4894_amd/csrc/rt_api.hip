@@ -214,7 +214,13 @@ struct TraceEntry {
   double interactions = 0.0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;   // recorded after every launch of the graph
   ~TraceEntry() {
+    // an evicted entry may still be running: its buffers are freed only after it ends
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   }
@@ -676,12 +682,19 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
     g.cache.push_back(std::move(fresh));
     e = g.cache.back().get();
   }
+  // Launches of one cached configuration share its work queue and FP32 copies: a
+  // launch on another stream waits for the previous one instead of racing it.
+  if (!e->done)
+    RT_HIP(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+  else
+    RT_HIP(hipStreamWaitEvent(stream, e->done, 0));
   if (g.timing) {
     if (!g.ev0) RT_HIP(hipEventCreate(&g.ev0));
     if (!g.ev1) RT_HIP(hipEventCreate(&g.ev1));
     RT_HIP(hipEventRecord(g.ev0, stream));
   }
   RT_HIP(hipGraphLaunch(e->exec, stream));
+  RT_HIP(hipEventRecord(e->done, stream));
   if (g.timing) RT_HIP(hipEventRecord(g.ev1, stream));
   g.timed_last = g.timing;
   g.last.kernel_ms = 0.0;

@@ -237,6 +237,30 @@ def test_particle_array_shared_by_two_frames():
     _check_fp32(g32, o, o["theta"])
 
 
+def test_one_configuration_on_two_streams_is_serialised():
+    """Two launches of one cached configuration on different streams, with no host wait
+    between them, give what the same two launches give on one stream (they share the
+    work queue and the FP32 copies, so the second waits for the first)."""
+    from paper_1110_4894_amd.runner import GpuRun
+    w = _small_nfw(n_part=900, n_side=3, n_fine=60)
+    g = GpuRun(w)
+    g.run(FP32K)                               # builds and captures the configuration
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def twice(a, b):
+        g.build_bundles()
+        torch.cuda.synchronize()
+        g.trace(FP32K, stream=a)
+        g.trace(FP32K, stream=b)
+        torch.cuda.synchronize()
+        assert rt.rt_last_trace_info()["graph_reused"] == 1
+        return g.rays.cpu().numpy()
+
+    same = twice(s1, s1)
+    assert np.array_equal(twice(s1, s2), same)
+    assert np.array_equal(twice(s2, s1), same)
+
+
 def test_graph_replay_follows_new_masses():
     """The equal-mass test runs inside the captured graph: a replay after the masses
     changed in place (same pointers, so the graph is reused) takes the general loop."""
