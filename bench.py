@@ -103,7 +103,7 @@ def parse():
                    help="bundles per step of the single-field workloads (nfw, box18, box20): 7168 bundles = "
                         "1024 groups of 7 bundles, two full rounds of the 512 workgroups that the trace kernel "
                         "keeps resident on 256 CUs")
-    p.add_argument("--side", type=int, default=16, help="bundle grid side of each field of the batched workload")
+    p.add_argument("--side", type=int, default=32, help="bundle grid side of each field of the batched workload")
     p.add_argument("--precision", default="fp32k", choices=["fp32k", "fp64"])
     p.add_argument("--fp64-stride", type=int, default=1,
                    help="every k-th bundle of the first timed batch is traced again in FP64")
