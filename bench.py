@@ -25,7 +25,9 @@ fields traced in one launch, --side x --side bundles per field); and the
 particle-mesh field: nfw_pm (the NFW band through a --pm-n^3 mesh, RK4 in z or,
 with --pm-frk, in the affine parameter), box18_pm / box20_pm (every bundle of the
 box grid through one periodic mesh per replica), pm_study (minimum reliable
-radius of the point lens against mesh resolution and n_int).
+radius of the point lens against mesh resolution and n_int), nfw_study (the NFW
+lens's minimum reliable radius against mesh, n_int, f_RK, bundle radius and
+particle mass, RK4 in the affine parameter).
 
 Prints one JSON line.
 """
@@ -34,6 +36,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -90,7 +93,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="nfw",
                    choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm", "box18_pm", "box20_pm",
-                            "pm_study"])
+                            "pm_study", "nfw_study"])
     p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid(s)")
     p.add_argument("--pm-compare-stride", type=int, default=0,
                    help="box*_pm: trace every k-th bundle of the grid with the direct sum too (0: 9 for box18, none "
@@ -211,6 +214,8 @@ def main():
         return bench_box_pm(a, torch, rt, workloads, GpuRun, dev)
     if a.workload == "pm_study":
         return bench_pm_study(a, torch, rt, workloads, dev)
+    if a.workload == "nfw_study":
+        return bench_nfw_study(a, torch, rt, workloads, dev)
 
     t_setup = time.time()
     w, desc = build_workload(a)
@@ -608,6 +613,133 @@ def bench_pm_study(a, torch, rt, workloads, dev):
                       "config": {"workload": "point lens 1e12 Msun at z_l 0.25, z_s 0.5, 32x32 bundles at 0.5-10 "
                                              "theta_E; isolated mesh of half-width 25 theta_E chi_l around it",
                                  "name": "pm_study"},
+                      "rows": rows}), flush=True)
+
+
+def nfw_mu_thin_lens(R, rs, rho_s, m_vir, r_vir, d_l, d_s, d_ls, G):
+    """Thin-lens magnification of the NFW profile (App. D: convergence and shear of the
+    projected profile) inside the virial radius, and of the point mass M_vir outside it
+    (the truncated halo's exterior, Sec. 4.2).  R: projected physical radius (Mpc); G: G/c^2 in
+    Mpc per Msun."""
+    sigma_cr = d_s / (4.0 * math.pi * G * d_l * d_ls)
+    kappa_s = rho_s * rs / sigma_cr
+    x = np.asarray(R, dtype=np.float64) / rs
+    F = np.empty_like(x)
+    H = np.empty_like(x)
+    lo, hi, one = x < 1.0 - 1e-9, x > 1.0 + 1e-9, np.abs(x - 1.0) <= 1e-9
+    xl, xh = x[lo], x[hi]
+    al = 2.0 / np.sqrt(1.0 - xl * xl) * np.arctanh(np.sqrt((1.0 - xl) / (1.0 + xl)))
+    ah = 2.0 / np.sqrt(xh * xh - 1.0) * np.arctan(np.sqrt((xh - 1.0) / (xh + 1.0)))
+    F[lo] = (1.0 - al) / (xl * xl - 1.0)
+    F[hi] = (1.0 - ah) / (xh * xh - 1.0)
+    F[one] = 1.0 / 3.0
+    H[lo] = np.log(xl / 2.0) + al
+    H[hi] = np.log(xh / 2.0) + ah
+    H[one] = 1.0 + np.log(0.5)
+    kappa = 2.0 * kappa_s * F
+    kbar = 4.0 * kappa_s * H / (x * x)
+    gamma = kbar - kappa
+    mu_in = 1.0 / ((1.0 - kappa) ** 2 - gamma ** 2)
+    th2 = (np.asarray(R) / d_l) ** 2
+    th_e2 = 4.0 * G * m_vir * d_ls / (d_l * d_s)
+    mu_out = 1.0 / (1.0 - (th_e2 / th2) ** 2)
+    return np.where(np.asarray(R) < r_vir, mu_in, mu_out)
+
+
+def bench_nfw_study(a, torch, rt, workloads, dev):
+    """The NFW parameter studies of Sec. 4.2 (Figs. 2-4) with the paper's integrator (RK4 in
+    the affine parameter, eq. RKstepsize) through an isolated particle-mesh field: the halo of
+    M_vir = 1e14 Msun, c = 7.2 at z_l = 0.35 (source z_s = 0.8) sampled with equal-mass
+    particles; bundles at 0.01-2 r_vir, log-uniform, against the thin-lens NFW magnification.
+    One parameter changes at a time from the fiducial (24 h^-1 kpc mesh, n_int = 2, f_RK = 1/2,
+    r_b = 0.1 arcsec, m_p = 1e10 Msun), and the mesh spacing again at m_p = 1e9 Msun, where the
+    particle noise no longer hides it.  Reported per run: the minimum reliable radius (the
+    smallest bin edge beyond which every log bin's mean |dmu/mu| is below 3%) and the median
+    error between it and r_vir."""
+    cos = workloads.Cosmology()
+    z_l, z_s, m_vir, conc = 0.35, 0.8, 1e14, 7.2
+    c = rt.cosmology(cos.omega_m, cos.omega_lambda, cos.h)
+    chi_s = rt.rt_comoving_distance(c, z_s)
+    chi_l = cos.comoving(z_l)
+    d_l, d_s, d_ls = chi_l / (1 + z_l), chi_s / (1 + z_s), (chi_s - chi_l) / (1 + z_s)
+    r_vir = (3.0 * m_vir / (4.0 * math.pi * 200.0 * cos.rho_crit(z_l))) ** (1.0 / 3.0)     # physical Mpc
+    rs = r_vir / conc
+    rho_s = 200.0 / 3.0 * conc ** 3 / (math.log(1 + conc) - conc / (1 + conc)) * cos.rho_crit(z_l)
+    rng = np.random.default_rng(np.random.SeedSequence(workloads.MASTER_SEED + 42))
+    nb = 4096
+    xr = np.exp(rng.uniform(np.log(0.01), np.log(2.0), nb))          # R / r_vir
+    phi = rng.uniform(0.0, 2.0 * np.pi, nb)
+    R = xr * r_vir
+    want = nfw_mu_thin_lens(R, rs, rho_s, m_vir, r_vir, d_l, d_s, d_ls, workloads.G_OVER_C2)
+    theta = torch.from_numpy(np.ascontiguousarray(np.stack([R / d_l * np.cos(phi), R / d_l * np.sin(phi)]))).to(dev)
+    nodes = rt.rt_make_schedule(chi_s, 0.0, chi_s, 100, 1.0)
+    empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(len(nodes) - 1, -1, np.int32),
+                            "bundle_offset": 0, "n_bundles": nb}])
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    steps = torch.zeros(9 * nb, dtype=torch.int32, device=dev)
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    edges = np.geomspace(0.01, 2.0, 22)
+    fid = {"h_kpc_h": 24.0, "n_int": 2, "f_rk": 0.5, "r_b_arcsec": 0.1, "m_p": 1e10}
+    runs = [("fiducial", {}), ("r_b 1 arcsec", {"r_b_arcsec": 1.0}), ("n_int 1", {"n_int": 1}),
+            ("mesh 49 h^-1 kpc", {"h_kpc_h": 49.0}), ("f_RK 1/4", {"f_rk": 0.25}),
+            ("m_p 1e9", {"m_p": 1e9}), ("m_p 1e11", {"m_p": 1e11}),
+            ("m_p 1e9, mesh 49 h^-1 kpc", {"m_p": 1e9, "h_kpc_h": 49.0}),
+            ("m_p 1e9, mesh 12 h^-1 kpc", {"m_p": 1e9, "h_kpc_h": 12.0})]
+    halos, grids = {}, {}
+    rows = []
+    for name, change in runs:
+        p = dict(fid, **change)
+        n_part = int(round(m_vir / p["m_p"]))
+        if n_part not in halos:
+            xyz, m, _ = workloads.nfw_halo_spec(cos, m_vir, conc, z_l, n_part,
+                                                np.random.default_rng(np.random.SeedSequence(workloads.MASTER_SEED
+                                                                                             + n_part)),
+                                                (0.0, 0.0, chi_l))
+            halos[n_part] = torch.from_numpy(np.ascontiguousarray(np.concatenate([xyz.T, m[None]], 0))).to(dev)
+        h = p["h_kpc_h"] * 1e-3 / cos.h                              # comoving mesh spacing
+        n = {12.0: 512, 24.0: 256, 49.0: 128}[p["h_kpc_h"]]          # half-width 4.4 Mpc each
+        key = (n_part, n)
+        if key not in grids:
+            grids.clear()
+            half = 0.5 * h * (n - 1)
+            grid = rt.pm_grid(n, (-half, -half, chi_l - half), h)
+            nbytes = rt.rt_pm_workspace_bytes(grid)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            fields = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+            rt.rt_pm_build(rt.make_particle_set(halos[n_part]), grid, fields, ws, nbytes)
+            del ws
+            grids[key] = (grid, fields)
+        grid, fields = grids[key]
+        r_b = p["r_b_arcsec"] * workloads.ARCSEC
+        rt.rt_build_bundles(c, empty, nb, theta, r_b, rays)
+        flags.zero_()
+        t0 = time.perf_counter()
+        rt.rt_trace_pm_lambda(c, z_s, grid, fields, p["n_int"], p["f_rk"], 1 << 30, nb, rays, flags, steps)
+        rt.rt_magnification(c, z_s, nb, r_b, rays, mu, None)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        err = np.abs(mu.cpu().numpy() / want - 1)
+        bins = np.digitize(xr, edges) - 1
+        mean = np.array([err[bins == k].mean() if np.any(bins == k) else 0.0 for k in range(len(edges) - 1)])
+        bad = np.nonzero(mean >= 0.03)[0]
+        mrr = float(edges[bad.max() + 1]) if bad.size else float(edges[0])
+        inner = (xr >= mrr) & (xr < 1.0)
+        rows.append({"run": name, "n_part": n_part, "mesh_kpc": h * 1e3, "n": n, "n_int": p["n_int"],
+                     "f_rk": p["f_rk"], "r_b_arcsec": p["r_b_arcsec"], "mrr_r_vir": mrr,
+                     "median_err_mrr_to_r_vir": float(np.median(err[inner])) if inner.any() else None,
+                     "median_err_beyond_r_vir": float(np.median(err[xr >= 1.0])),
+                     "rk4_steps_per_ray": float(steps.double().mean()), "flagged_rays": int((flags != 0).sum()),
+                     "trace_ms": ms})
+        print("%s: MRR %.3f r_vir, median error %.4f inside, %.4f outside, %.0f steps, %.0f ms"
+              % (name, mrr, rows[-1]["median_err_mrr_to_r_vir"] or float("nan"), rows[-1]["median_err_beyond_r_vir"],
+                 rows[-1]["rk4_steps_per_ray"], ms), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "minimum reliable radius of the NFW lens through the mesh field (3% of the thin-lens mu)",
+                      "unit": "r_vir", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "NFW M_vir 1e14 Msun, c 7.2, z_l 0.35, z_s 0.8 (r_vir %.3f Mpc physical), "
+                                             "%d bundles at 0.01-2 r_vir; isolated meshes of half-width 4.4 Mpc; RK4 in "
+                                             "the affine parameter" % (r_vir, nb),
+                                 "name": "nfw_study"},
                       "rows": rows}), flush=True)
 
 
