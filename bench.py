@@ -27,7 +27,8 @@ with --pm-frk, in the affine parameter), box18_pm / box20_pm (every bundle of th
 box grid through one periodic mesh per replica), pm_study (minimum reliable
 radius of the point lens against mesh resolution and n_int), nfw_study (the NFW
 lens's minimum reliable radius against mesh, n_int, f_RK, bundle radius and
-particle mass, RK4 in the affine parameter).
+particle mass, RK4 in the affine parameter), soft_study (the box's muPDF and
+shear PDF at three particle softenings).
 
 Prints one JSON line.
 """
@@ -93,7 +94,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="nfw",
                    choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm", "box18_pm", "box20_pm",
-                            "pm_study", "nfw_study"])
+                            "pm_study", "nfw_study", "soft_study"])
     p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid(s)")
     p.add_argument("--pm-compare-stride", type=int, default=0,
                    help="box*_pm: trace every k-th bundle of the grid with the direct sum too (0: 9 for box18, none "
@@ -216,6 +217,8 @@ def main():
         return bench_pm_study(a, torch, rt, workloads, dev)
     if a.workload == "nfw_study":
         return bench_nfw_study(a, torch, rt, workloads, dev)
+    if a.workload == "soft_study":
+        return bench_soft_study(a, torch, rt, workloads, GpuRun, dev)
 
     t_setup = time.time()
     w, desc = build_workload(a)
@@ -613,6 +616,45 @@ def bench_pm_study(a, torch, rt, workloads, dev):
                       "config": {"workload": "point lens 1e12 Msun at z_l 0.25, z_s 0.5, 32x32 bundles at 0.5-10 "
                                              "theta_E; isolated mesh of half-width 25 theta_E chi_l around it",
                                  "name": "pm_study"},
+                      "rows": rows}), flush=True)
+
+
+def bench_soft_study(a, torch, rt, workloads, GpuRun, dev):
+    """The softening comparison of Sec. 5.4 (Fig. 7) on the 2^18-particle Zel'dovich box:
+    the source-weighted muPDF (eq. weighthisto) and shear PDF of the 128 x 128 bundle grid,
+    0.1 arcsec bundles, traced with the direct sum (FP32 pair terms) at three Plummer
+    softenings: the paper's 5 and 16 h^-1 kpc and the workload's 50 h^-1 kpc."""
+    rows = []
+    for soft in (5.0, 16.0, 50.0):
+        w = workloads.box(n_part_log2=18, n_side=128, soft_kpc_h=soft)
+        g = GpuRun(w)
+        t0 = time.perf_counter()
+        out = g.run(rt.RT_FP32_KAHAN)
+        pdf, mom = g.histogram(200, -0.1, 0.3)
+        gpdf = torch.empty(100, dtype=torch.float64, device=dev)
+        gmom = torch.empty(6, dtype=torch.float64, device=dev)
+        rt.rt_shear_histogram(g.n_bundles, g.mu, g.jac, 100, 0.0, 0.1, gpdf, gmom)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        mu = out["mu"]
+        m = mom.cpu().numpy()
+        gm = gmom.cpu().numpy()
+        p = pdf.cpu().numpy()
+        centres = 10 ** (-0.1 + 0.4 * (np.arange(200) + 0.5) / 200)
+        rows.append({"softening_kpc_h": soft, "bundles": int(mu.size), "mean_mu_w": float(m[1]),
+                     "sigma_mu_w": float(m[2]), "mu_peak": float(centres[int(np.argmax(p))]),
+                     "frac_mu_gt_1p5": float(np.mean(mu > 1.5)), "frac_mu_gt_3": float(np.mean(mu > 3.0)),
+                     "n_mu_le_0": int(m[3]), "mean_shear_w": float(gm[1]), "sigma_shear_w": float(gm[2]),
+                     "max_mu": float(mu.max()), "flagged_rays": int((out["flags"] != 0).sum()), "seconds": sec})
+        print("softening %g h^-1 kpc: <mu>_w %.5f, sigma %.4f, peak %.4f, P(mu>1.5) %.2e, %.0f s"
+              % (soft, m[1], m[2], rows[-1]["mu_peak"], rows[-1]["frac_mu_gt_1p5"], sec), file=sys.stderr,
+              flush=True)
+        del g
+    print(json.dumps({"metric": "muPDF and shear PDF of the box against the particle softening",
+                      "unit": "", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "2^18-particle Zel'dovich box (100 h^-1 Mpc, 14 replicas to z_s 0.5), "
+                                             "128x128 bundles of 0.1 arcsec over 1 deg, 2000 RK4 steps, FP32 pair "
+                                             "terms", "name": "soft_study"},
                       "rows": rows}), flush=True)
 
 
