@@ -129,7 +129,10 @@ rt_status rt_build_bundles(const rt_cosmology* cosmo, const rt_field* fields, in
  * Field at each stage: direct sum over the step's particle set plus the optional cuboid
  * background; Christoffel symbols differentiated exactly from eq. expandingmetric.
  * All fields are traced in one persistent launch with a work queue, captured once in a HIP
- * graph and replayed while the arguments stay the same.
+ * graph and replayed while the arguments stay the same; launches of one such configuration on
+ * different streams are ordered one after the other (they share its FP32 copies and queue).
+ * RT_FP32_KAHAN: a set whose masses are all equal (checked on the device at every call) takes
+ * a loop that stages positions only and scales the sums by the common mass.
  * rays: device [8][9 n_bundles], updated in place.  ray_flags: device [9 n_bundles] or NULL;
  * bits are OR-ed in: 1 non-finite state, 2 kz <= 0 (ray turned back), 4 |phi|/a > 1e-2 (outside
  * the weak-field regime of Sec. 3.2).  A ray with flag 1 or 2 keeps its last good state.
