@@ -84,6 +84,10 @@ MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309
                     "799090d3d3da2c72": {"read": 527069855930.1256, "write": 65751117760.0},
                     "ae59e4cd8fd79606": {"read": 438975467239.04016, "write": 28242255520.0},
                     "88c0e800b45ed36d": {"read": 255562822694.14062, "write": 37611626752.0,
+                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"},
+                    # a comment-only change of the source above: the gfx950 assembly differs only in
+                    # the compilation-unit id symbol
+                    "6aaff9f945547e36": {"read": 255562822694.14062, "write": 37611626752.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 

@@ -9,8 +9,9 @@
 // them, combining their partial sums through LDS in a fixed order.
 //
 // Design notes for CDNA4:
-//   * pair terms are plain VALU work: 13 FP32 VALU operations per pair plus one
-//     v_rsq_f32.  (A matrix-core form of the sum exists, but the FP32 frame of
+//   * pair terms are plain VALU work: 13 FP32 VALU operations per pair with one
+//     v_rsq_f32 among them, 12 for sets of equal masses (whose copies hold
+//     positions only, four particles in three float4).  (A matrix-core form of the sum exists, but the FP32 frame of
 //     a bundle can be shared by at most the 4 rays of a 4x4x1 block, and that
 //     MFMA shape runs slower than the VALU loop on gfx950.)
 //   * the FP32 path works in a frame per bundle: each 64-particle tile is
