@@ -222,6 +222,22 @@ def test_box_parity_with_background():
     _check_fp32(g32, o, o["theta"])
 
 
+def test_empty_replicas_keep_their_background():
+    """Degenerate sets: every other replica of the box holds no particles (n = 0), so only
+    its uniform-cuboid term acts there (an empty, underdense region)."""
+    w = _small_box()
+    f = w.fields[0]
+    sets = [dataclasses.replace(s, xyz=np.zeros((0, 3)), m=np.zeros(0)) if k % 2 == 0 else s
+            for k, s in enumerate(f.sets)]
+    w2 = dataclasses.replace(w, fields=[dataclasses.replace(f, sets=sets)])
+    o = oracle_run(w2)
+    assert np.all(o["mu"] < 1.0)
+    g64, _ = _run(w2, FP64)
+    _check_fp64(g64, o, o["theta"])
+    g32, _ = _run(w2, FP32K)
+    _check_fp32(g32, o, o["theta"])
+
+
 def test_particle_array_shared_by_two_frames():
     """One particle array in two fields, with and without its background cuboid:
     the two sets have different FP32 frames, so each gets its own FP32 copy."""
