@@ -106,6 +106,15 @@ def test_argument_errors(lib):
     cub = {"xyzm": None, "softening": 0.1, "background": True, "lo": (0, 0, 1), "hi": (1, 1, 0)}
     with_cub = dict(good, sets=[cub], step_set=np.zeros(10, np.int32))
     assert _status(rt.rt_trace, c, 0.5, rt.FieldTable([with_cub]), 0, 0, 10, 2, fake) == -1
+    # the largest set is 2^31 particles (a 32 GB FP32 copy); one more is refused
+    class _Huge:
+        shape = (4, (1 << 31) + 1)
+
+        def data_ptr(self):
+            return fake
+    huge = dict(good, sets=[{"xyzm": _Huge(), "softening": 0.0}], step_set=np.zeros(10, np.int32))
+    assert _status(rt.rt_trace, c, 0.5, rt.FieldTable([huge]), 0, 0, 10, 2, fake) == -7
+    assert "2^31" in rt.rt_last_error()
     assert _status(rt.rt_build_bundles, c, rt.FieldTable([]), 2, fake, 0.1, fake) == -1     # radius too large
     assert _status(rt.rt_build_bundles, c, rt.FieldTable([]), 0, fake, 1e-8, fake) == -1
     assert _status(rt.rt_magnification, c, 0.5, 2, 0.0, fake, fake) == -1
