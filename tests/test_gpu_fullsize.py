@@ -9,7 +9,8 @@ schedules), on sampled bundles that the CPU oracle traces one by one.
 * Zel'dovich boxes (2^18 and 2^20 particles in 14 replicas, 2000 steps): bands of
   bundles in FP32, sampled bundles against the oracle;
 * 64 uneven fields in one launch (bundle grids reduced to 8 x 8 per field):
-  FP32 vs FP64 over every bundle and the oracle on one bundle of several fields.
+  FP32 vs FP64 over every bundle and the oracle on one bundle of several fields;
+* the largest sets: the field of a 7.2e8-particle set (offsets beyond 2^31 elements).
 Tolerances as in test_gpu_parity.py.
 """
 import math
@@ -158,3 +159,45 @@ def test_uneven_fields_one_launch():
     sub32 = {"mu": g32["mu"][keep], "flags": g32["flags"][rays_idx], "rays": g32["rays"][:, rays_idx],
              "chi_s": g32["chi_s"]}
     _check_fp32(sub32, o, o["theta"])
+
+
+def test_set_beyond_32bit_offsets():
+    """The largest sets: 7.2e8 particles, so that the z and mass columns of the caller's
+    [4][n] array start beyond 2^31 elements.  The last 1000 particles carry mass and the rest
+    none (their terms are exactly zero in either precision), so the oracle sums the massive
+    ones only; the field at 63 points against it, FP64 and FP32."""
+    n, k = 720_000_000, 1000
+    assert 3 * n > 2 ** 31
+    rng = np.random.default_rng(np.random.SeedSequence(wl.MASTER_SEED + 7))
+    xyz = rng.normal(size=(k, 3)) * 0.3 + np.array([0.1, -0.2, 1000.0])
+    m = rng.uniform(1e9, 1e11, k)
+    pts = rng.normal(size=(3, 63)) * 0.2 + np.array([[0.0], [0.0], [1000.0]])
+    eps = 0.01
+    c = orc.cosmo()
+    ps = orc.ParticleSet(xyz=xyz, m=m, softening=eps)
+    ref_phi = np.zeros(63)
+    ref_g = np.zeros((3, 63))
+    for i in range(63):
+        ref_phi[i], ref_g[:, i] = orc.field_at(c, ps, pts[:, i])
+    dev = torch.device("cuda")
+    _say("allocating a [4][%d] set (%.1f GB)" % (n, 32e-9 * n))
+    xyzm = torch.empty((4, n), dtype=torch.float64, device=dev)
+    xyzm[0].fill_(0.1)
+    xyzm[1].fill_(-0.2)
+    xyzm[2].fill_(1000.0)
+    xyzm[3].zero_()
+    xyzm[:, n - k:] = torch.from_numpy(np.ascontiguousarray(np.concatenate([xyz.T, m[None]], 0))).to(dev)
+    pset = rt.make_particle_set(xyzm, eps)
+    P = torch.from_numpy(np.ascontiguousarray(pts)).to(dev)
+    for prec, tol in ((FP64, 1e-12), (FP32K, 3e-5)):
+        phi = torch.empty(63, dtype=torch.float64, device=dev)
+        grad = torch.empty((3, 63), dtype=torch.float64, device=dev)
+        rt.rt_field_eval(rt.cosmology(), pset, prec, 63, P, phi, grad)
+        rt.rt_sync()
+        _say("field over %d particles, precision %d: done" % (n, prec))
+        gphi, gg = phi.cpu().numpy(), grad.cpu().numpy()
+        assert np.all(np.abs(gphi - ref_phi) <= tol * np.abs(ref_phi)), prec
+        scale = np.linalg.norm(ref_g, axis=0)
+        assert np.all(np.abs(gg - ref_g) <= tol * scale + 1e-30), prec
+    del xyzm
+    torch.cuda.empty_cache()
