@@ -684,9 +684,14 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
   }
   // Launches of one cached configuration share its work queue and FP32 copies: a
   // launch on another stream waits for the previous one instead of racing it.
+  // (Not while the caller's stream is being captured: an event recorded outside a
+  // capture cannot be waited on inside it.)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  RT_HIP(hipStreamIsCapturing(stream, &cap));
+  const bool ordered = cap == hipStreamCaptureStatusNone;
   if (!e->done)
     RT_HIP(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
-  else
+  else if (ordered)
     RT_HIP(hipStreamWaitEvent(stream, e->done, 0));
   if (g.timing) {
     if (!g.ev0) RT_HIP(hipEventCreate(&g.ev0));
@@ -694,7 +699,7 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
     RT_HIP(hipEventRecord(g.ev0, stream));
   }
   RT_HIP(hipGraphLaunch(e->exec, stream));
-  RT_HIP(hipEventRecord(e->done, stream));
+  if (ordered) RT_HIP(hipEventRecord(e->done, stream));
   if (g.timing) RT_HIP(hipEventRecord(g.ev1, stream));
   g.timed_last = g.timing;
   g.last.kernel_ms = 0.0;
