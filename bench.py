@@ -88,6 +88,10 @@ MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309
                     # a comment-only change of the source above: the gfx950 assembly differs only in
                     # the compilation-unit id symbol
                     "6aaff9f945547e36": {"read": 255562822694.14062, "write": 37611626752.0,
+                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"},
+                    # the FP64 equal-mass loop: trace_kernel<false, 8, 8, 64> compiles to the same
+                    # gfx950 assembly (diffed)
+                    "209f5451189981e7": {"read": 255562822694.14062, "write": 37611626752.0,
                                          "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
 
 

@@ -384,16 +384,16 @@ rt_status build_entry(TraceEntry* e, const DeviceInfo& di, const rt_cosmology& c
         ds.hi[k] = s.hi[k];
       }
       ds.p32 = nullptr;
-      if (!fp64 && s.n > 0) {
+      if (s.n > 0) {
         std::array<double, 6> box{};
         if (s.background) box = {s.lo[0], s.lo[1], s.lo[2], s.hi[0], s.hi[1], s.hi[2]};
         const ConvKey key{s.xyzm, s.n, s.background, box};
         auto it = p32_of.find(key);
         if (it == p32_of.end()) {
-          float4* p;
+          float4* p = nullptr;   // FP64 traces keep no copy; their masses are still checked
           int32_t* eq;
-          rt_status st = dev_alloc(e, &p, (size_t)s.n);
-          if (st != RT_OK) return st;
+          rt_status st;
+          if (!fp64 && (st = dev_alloc(e, &p, (size_t)s.n)) != RT_OK) return st;
           if ((st = dev_alloc(e, &eq, 1)) != RT_OK) return st;
           it = p32_of.emplace(key, std::make_pair(p, eq)).first;
           e->conv.push_back({(int32_t)hs.size(), s.xyzm, p, s.n});
@@ -786,11 +786,11 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
   DevSet* d_set = static_cast<DevSet*>(scratch);
   float4* p32 = reinterpret_cast<float4*>(static_cast<char*>(scratch) + p32_off);
   hs.p32 = p32_bytes ? p32 : nullptr;
-  hs.equal_mass = p32_bytes ? reinterpret_cast<int32_t*>(static_cast<char*>(scratch) + flag_off) : nullptr;
+  hs.equal_mass = set->n > 0 ? reinterpret_cast<int32_t*>(static_cast<char*>(scratch) + flag_off) : nullptr;
   RT_HIP(hipMemcpyAsync(d_set, &hs, sizeof(DevSet), hipMemcpyHostToDevice, stream));
   RT_HIP(hipStreamSynchronize(stream));   // hs is a local
   RT_HIP(launch_prepare_sets(d_set, 1, stream));
-  if (p32_bytes) RT_HIP(launch_convert_set(d_set, set->xyzm, p32, set->n, stream));
+  if (set->n > 0) RT_HIP(launch_convert_set(d_set, set->xyzm, hs.p32, set->n, stream));
   RT_HIP(launch_field_eval(dc, d_set, fp64, n, points, phi, grad, stream));
   RT_HIP(hipFreeAsync(scratch, stream));
   return RT_OK;

@@ -24,7 +24,7 @@ struct DevCosmo {
 struct DevSet {
   const double* p64;   // caller's [4][n] (x, y, z, m)
   float4* p32;         // library copy: (x - org, y - org, z - org, m) in FP32, [n]
-  int32_t* equal_mass; // with p32: 1 when every mass equals mass (set on the device), shared with p32
+  int32_t* equal_mass; // n > 0: 1 when every mass equals mass (set on the device), shared by the sets of one array
   int64_t n;
   double eps2;         // softening^2, FP64
   float eps2f;         // softening^2, FP32

@@ -276,8 +276,24 @@ __device__ __forceinline__ void pair_fp64(const double4 c, double x, double y, d
   a3 = fma(mr3, ez, a3);
 }
 
+// The same with unit mass (sets of equal masses: the caller scales the sums).
+__device__ __forceinline__ void pair_fp64_unit(const double4 c, double x, double y, double z, double e2,
+                                               double& a0, double& a1, double& a2, double& a3) {
+  const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
+  double r2 = fma(ex, ex, e2);
+  r2 = fma(ey, ey, r2);
+  r2 = fma(ez, ez, r2);
+  const double ri = rsqrt_f64(r2);
+  a0 += ri;
+  const double r3 = ri * ri * ri;
+  a1 = fma(r3, ex, a1);
+  a2 = fma(r3, ey, a2);
+  a3 = fma(r3, ez, a3);
+}
+
 // FP64 path: tiles of the caller's FP64 particles, broadcast to every lane.
-template <int T, int WPR>
+// UNIT: every mass equals s.mass, which multiplies the finished sums.
+template <int T, int WPR, bool UNIT>
 __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, int lane, double x, double y,
                                          double z, double& S0, double& Sx, double& Sy, double& Sz) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -297,17 +313,24 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, 
     const int64_t left = n - base;   // the set's last tile runs only over its particles
     if (left >= T) {
 #pragma unroll 8
-      for (int k = 0; k < T; ++k) pair_fp64(tile[k], x, y, z, e2, a0, a1, a2, a3);
+      for (int k = 0; k < T; ++k) {
+        if constexpr (UNIT) pair_fp64_unit(tile[k], x, y, z, e2, a0, a1, a2, a3);
+        else pair_fp64(tile[k], x, y, z, e2, a0, a1, a2, a3);
+      }
     } else {
 #pragma unroll 1
-      for (int k = 0; k < (int)left; ++k) pair_fp64(tile[k], x, y, z, e2, a0, a1, a2, a3);
+      for (int k = 0; k < (int)left; ++k) {
+        if constexpr (UNIT) pair_fp64_unit(tile[k], x, y, z, e2, a0, a1, a2, a3);
+        else pair_fp64(tile[k], x, y, z, e2, a0, a1, a2, a3);
+      }
     }
     wave_sync();
   }
-  S0 = a0;
-  Sx = a1;
-  Sy = a2;
-  Sz = a3;
+  const double m = UNIT ? s.mass : 1.0;
+  S0 = m * a0;
+  Sx = m * a1;
+  Sy = m * a2;
+  Sz = m * a3;
 }
 
 // LDS needed by one wavefront's tiles.
@@ -331,7 +354,10 @@ struct FieldEval {
                               bool red_in_tiles = false) {
     double S0, Sx, Sy, Sz;
     if constexpr (F64) {
-      sum_fp64<T, WPR>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
+      if (s.equal_mass && *s.equal_mass)
+        sum_fp64<T, WPR, true>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
+      else
+        sum_fp64<T, WPR, false>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
     } else {
       // positions in the set's frame (FP64), each bundle's anchor rounded to FP32
       const double X = x - s.org[0], Yv = y - s.org[1], Z = z - s.org[2];
@@ -587,7 +613,8 @@ __global__ void convert_set_kernel(const DevSet* set, const double* p64, float4*
   if (j >= n) return;
   const double ox = set->org[0], oy = set->org[1], oz = set->org[2];
   const double m = p64[3 * n + j];
-  p32[j] = make_float4((float)(p64[j] - ox), (float)(p64[n + j] - oy), (float)(p64[2 * n + j] - oz), (float)m);
+  if (p32)   // (FP64 sets have no copy: only their masses are checked)
+    p32[j] = make_float4((float)(p64[j] - ox), (float)(p64[n + j] - oy), (float)(p64[2 * n + j] - oz), (float)m);
   if (!(m == p64[3 * n])) *set->equal_mass = 0;   // (a NaN mass also takes the general path)
 }
 

@@ -194,7 +194,7 @@ def _unequal_masses(w, seed=11):
     return dataclasses.replace(w, fields=fields)
 
 
-@pytest.mark.parametrize("prec,masses", [(FP64, "equal"), (FP32K, "equal"), (FP32K, "unequal")])
+@pytest.mark.parametrize("prec,masses", [(FP64, "equal"), (FP64, "unequal"), (FP32K, "equal"), (FP32K, "unequal")])
 def test_every_plan_passes_parity(prec, masses):
     w = _small_nfw(n_part=2049, n_side=5, n_fine=60)
     if masses == "unequal":
