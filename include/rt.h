@@ -3,12 +3,12 @@
  *
  * Method: Killedar, Lasky, Lewis & Fluke (2011), "Gravitational lensing with
  * three-dimensional ray tracing".  Bundles of one central ("anchor") ray and
- * 8 ring rays (Sec. 2.4, 3.1) are integrated along null geodesics (Sec. 3.4,
+ * 8 ring rays (Sec. 3.1) are integrated along null geodesics (Sec. 3.4,
  * eq. geodesiceqn) of the weakly perturbed flat FLRW metric (Sec. 3.2,
  * eq. expandingmetric, phicotophys), with the comoving potential of Plummer-
  * softened point masses (Sec. 3.3, eq. psi, derivs) summed directly at every
  * RK4 stage.  The distorted area of each bundle at the source plane gives the
- * magnification mu (Sec. 2.4, eq. magnification), and the source-weighted mu
+ * magnification mu (Sec. 3.1, eq. magnification), and the source-weighted mu
  * histogram (Sec. 5.3, eq. weighthisto) gives the muPDF.
  *
  * Conventions shared by all calls
@@ -111,7 +111,7 @@ rt_status rt_replica_step_sets(const double* nodes, int32_t n_steps, double box,
 
 /* ---------------------------------------------------------------- the hot path */
 
-/* Initial state of every ray (Sec. 2.4, 3.1, 3.4): anchor direction theta (gnomonic, so that
+/* Initial state of every ray (Sec. 3.1, 3.4): anchor direction theta (gnomonic, so that
  * straight rays reach z = chi_s at theta * chi_s), ring rays at theta + radius (cos pi k/4,
  * sin pi k/4); t = x = y = z = 0, kt = 1, (kx, ky, kz) = n sqrt(E0 / F0) with
  * E0 = 1 + 2 phi_obs, F0 = 1 - 2 phi_obs so that the wave vector is exactly null, phi_obs
@@ -141,7 +141,7 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
                    rt_precision precision, int32_t step_begin, int32_t step_end, int64_t n_bundles,
                    double* rays, uint8_t* ray_flags, hipStream_t stream);
 
-/* Magnification and Jacobian of each bundle at z = chi_s (Sec. 2.4, eq. lensmap, magnification):
+/* Magnification and Jacobian of each bundle at z = chi_s (Sec. 3.1, eq. lensmap, magnification):
  * offsets D_k = x_k - x_anchor (FP64); mu = (homogeneous octagon area chi_s^2 2 sqrt(2) r^2) /
  * (signed shoelace area of the traced octagon), negative for parity-flipped images;
  * Jacobian = least-squares linear map of the ring offsets: A = sum_k D_k u_k^T / (4 r^2 chi_s).
@@ -250,6 +250,7 @@ typedef struct rt_plan_info {
   int32_t waves_per_group;    /* wavefronts that share 63 rays and split the particles      */
   int32_t tile;               /* particles per LDS tile per wavefront                        */
   int32_t rays_per_block;     /* 63 * waves_per_block / waves_per_group (7 bundles per group) */
+  int32_t waves_per_simd;     /* occupancy the plan is compiled for (registers: 512 / it)    */
 } rt_plan_info;
 
 /* Number of compiled trace plans for a precision, and the shape of plan `id`. */

@@ -334,7 +334,7 @@ int or_replica_step_sets(const double* nodes, int32_t n_steps, double box, int32
 }
 
 /* ------------------------------------------------------------------------ */
-/* Ray bundles (Sec. 2.4 / 3.1: a central ray and 8 rays on a regular        */
+/* Ray bundles (Sec. 3.1: a central ray and 8 rays on a regular        */
 /* polygon).  Ring ray k sits at angle pi k / 4, counter-clockwise from +x.  */
 /* Directions are gnomonic, n ~ (theta_x, theta_y, 1), so that straight rays */
 /* reach the plane z = chi_s at theta * chi_s.  At the observer t = 0,       */
@@ -467,7 +467,7 @@ int or_trace(const or_cosmo* c, const or_field* fields, int32_t n_fields, int32_
 }
 
 /* ------------------------------------------------------------------------ */
-/* Magnification from the bundle at the source plane (Sec. 2.4, 3.1 and      */
+/* Magnification from the bundle at the source plane (Sec. 3.1 and      */
 /* eq. lensmap, magnification).  Offsets D_k = x_k - x_anchor at z = chi_s.  */
 /* mu = (area of the homogeneous octagon) / (signed area of the traced one); */
 /* the Jacobian is the least-squares linear map from the ring offsets u_k    */

@@ -393,7 +393,7 @@ rt_status build_entry(TraceEntry* e, const DeviceInfo& di, const rt_cosmology& c
           float4* p = nullptr;   // FP64 traces keep no copy; their masses are still checked
           int32_t* eq;
           rt_status st;
-          if (!fp64 && (st = dev_alloc(e, &p, (size_t)s.n)) != RT_OK) return st;
+          if (!fp64 && (st = dev_alloc(e, &p, 2 * (size_t)s.n)) != RT_OK) return st;
           if ((st = dev_alloc(e, &eq, 1)) != RT_OK) return st;
           it = p32_of.emplace(key, std::make_pair(p, eq)).first;
           e->conv.push_back({(int32_t)hs.size(), s.xyzm, p, s.n});
@@ -777,7 +777,7 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
     hs.lo[k] = set->lo[k];
     hs.hi[k] = set->hi[k];
   }
-  const size_t p32_bytes = (!fp64 && set->n > 0) ? sizeof(float4) * (size_t)set->n : 0;
+  const size_t p32_bytes = (!fp64 && set->n > 0) ? 2 * sizeof(float4) * (size_t)set->n : 0;
   // scratch: DevSet, its equal-mass flag, then (256-byte aligned) the FP32 copy
   const size_t flag_off = ((sizeof(DevSet) + 7) / 8) * 8;
   const size_t p32_off = ((flag_off + sizeof(int32_t) + 255) / 256) * 256;

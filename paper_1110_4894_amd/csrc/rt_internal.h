@@ -23,13 +23,15 @@ struct DevCosmo {
 // One particle set as the kernels see it.
 struct DevSet {
   const double* p64;   // caller's [4][n] (x, y, z, m)
-  float4* p32;         // library copy: (x - org, y - org, z - org, m) in FP32, [n]
+  float4* p32;         // library copy, [2][n] float4: (x - org, y - org, z - org, m / mref) rounded to
+                       // FP32, then the rounding residuals of the three coordinates (and 0)
   int32_t* equal_mass; // n > 0: 1 when every mass equals mass (set on the device), shared by the sets of one array
   int64_t n;
   double eps2;         // softening^2, FP64
   float eps2f;         // softening^2, FP32
   int32_t background;
   double mass;         // the first particle's mass (filled on the device)
+  double mref;         // unit of the FP32 copy's masses: mass, or 1 when that is 0 (filled on the device)
   double org[3];       // frame origin of p32 (filled on the device)
   double lo[3], hi[3]; // background cuboid
 };

@@ -2,24 +2,26 @@
 //
 // Method: Killedar, Lasky, Lewis & Fluke (2011).  The hot kernel is the
 // persistent trace kernel: every wavefront owns 7 whole bundles (63 rays, one
-// per lane) and integrates them through all RK4 steps; at every stage the
-// rays' field is the direct sum over the step's particle set (Sec. 3.3,
+// per lane) and integrates them through all RK4 steps in FP64; at every stage
+// the rays' field is the direct sum over the step's particle set (Sec. 3.3,
 // eq. psi, derivs), streamed in tiles through the wavefront's own LDS slice.
-// Several wavefronts may share the same rays and split the particles between
-// them, combining their partial sums through LDS in a fixed order.
 //
 // Design notes for CDNA4:
-//   * pair terms are plain VALU work: 13 FP32 VALU operations per pair with one
-//     v_rsq_f32 among them, 12 for sets of equal masses (whose copies hold
-//     positions only, four particles in three float4).  (A matrix-core form of the sum exists, but the FP32 frame of
-//     a bundle can be shared by at most the 4 rays of a 4x4x1 block, and that
-//     MFMA shape runs slower than the VALU loop on gfx950.)
-//   * the FP32 path works in a frame per bundle: each 64-particle tile is
-//     staged in LDS once per bundle as particle - anchor, and each lane holds
-//     its ray's small offset from its anchor, so the differences between the
-//     rays of a bundle keep full FP32 resolution;
-//   * plain FP32 partial sums over each 64-particle tile are added with Kahan
-//     compensation; FP64 is kept for the ray state and the integration;
+//   * FP32 field sums work per bundle (Sec. 3.1: an anchor and a ring of 8
+//     rays a few parsecs away).  The nine lanes of a bundle split the
+//     particles; each (bundle, particle) pair is evaluated once, at the
+//     bundle's expansion point, as the pair's potential and field and their
+//     first and second derivatives (20 moments, 36 VALU instructions and one
+//     v_rsq_f32 per pair, i.e. 4 per ray-particle interaction).  Every ray
+//     assembles its own field in FP64 from the moments and its exact offset.
+//     Ring-minus-anchor field differences, which carry the lensing signal,
+//     so keep FP32 relative precision: rounding each particle-ray
+//     displacement to FP32 instead would quantise the ring offset to the ulp
+//     of a Mpc-scale distance, identically for every particle of a binade;
+//   * plain FP32 partial sums over each tile are added with Kahan
+//     compensation; FP64 is kept for the ray state, the integration and the
+//     assembly of each ray's field;
+//   * the pairwise sum is not a dense contraction: no matrix cores;
 //   * work items (field, block of rays) are pulled from an atomic queue so that
 //     fields of very different particle counts share one launch.
 #include <hip/hip_runtime.h>
@@ -42,13 +44,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-
-__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
-  float y = v - c;
-  float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
 
 // FP64 reciprocal square root of a finite x > 0: the hardware estimate r
 // (relative error about 2^-24) refined with the second-order expansion of
@@ -106,161 +101,339 @@ __device__ void cuboid_field(const double lo[3], const double hi[3], double px, 
 }
 
 // ---------------------------------------------------------------------------
-// Field sums over one wavefront's share of a particle set.
-//
-// A wavefront holds 7 whole bundles: lane l < 63 owns ray l of the group
-// (bundle l / 9, ray l % 9 of it, the anchor first); lane 63 only helps.
-// Raw sums returned: S0 = sum m / r,  S = sum m (x_j - x) / r^3.
+// Lane layout shared by every kernel that holds bundles: a wavefront holds 7
+// whole bundles, lane l < 63 owns ray l of the group (bundle l / 9, ray l % 9
+// of it, the anchor first); lane 63 only helps to stage tiles.
 // ---------------------------------------------------------------------------
 constexpr int kLanes = 63;              // rays per wavefront
 constexpr int kSeg = 7;                 // bundles per wavefront
-constexpr int kTile32 = 64;             // particles per FP32 tile (one per lane)
-constexpr int kCopyStride = kTile32 + 1;  // float4 per bundle copy (+1 spreads the copies over LDS banks)
 
 __device__ __forceinline__ int lane_segment(int lane) { return lane < kLanes ? lane / 9 : kSeg - 1; }
 
-// FP32 path, equal masses: the staged copies hold positions only, four
-// particles in three float4 (x0 y0 z0 x1 | y1 z1 x2 y2 | z2 x3 y3 z3), so the
-// pair loop issues three LDS reads per four particles instead of four (the
-// loop is bound by VALU issue and LDS returns together); the caller multiplies
-// the unit-mass sums by the common mass.
-constexpr int kPackedStride = 3 * kTile32 / 4 + 1;   // float4 per bundle copy
-static_assert(kPackedStride <= kCopyStride, "the packed copies fit in the general tile");
+// ===========================================================================
+// FP32 field sums: bundle moments.
+//
+// A ray of a bundle sits at e + delta, where e is the bundle's expansion point
+// (its anchor rounded to FP32 in the set's frame, at the stage's z) and delta
+// = (dx, dy, 0) its own offset, a few parsecs (all rays of a field share z).
+// With D = x_j - e and s = |D|^2 + eps^2, one particle's terms at the ray,
+// m (s - 2 D.delta + |delta|^2)^(-1/2) and m (D - delta) (...)^(-3/2), expand
+// in delta; to second order the sums over the particles are
+//
+//   S0(delta) = Phi + G.delta - |delta|^2 W / 2 + 3/2 delta.T.delta
+//   S(delta)  = G + 3 T.delta - W delta - 3/2 |delta|^2 V - 3 delta (V.delta)
+//               + 15/2 U(delta, delta)
+//
+// with the moments (w = s^-3/2, q = s^-5/2, r = s^-7/2, sums over j of m_j x)
+//   Phi = m s^-1/2, G_i = m w D_i, W = m w, V_i = m q D_i, T_il = m q D_i D_l,
+//   U_ilk = m r D_i D_l D_k   (l, k over x and y only, as delta_z = 0).
+//
+// The expansion variable u = (|delta|^2 - 2 D.delta) / s has |u| <= 2 |delta|
+// / sqrt(s) + |delta|^2 / s; the first neglected terms are 35/16 u^3 of the
+// pair's field and 5/16 u^3 of its potential, i.e. about 1.5 u^2 and 0.6 u^2 of
+// the pair's ring-minus-anchor difference (its first-order term).  A pair is
+// summed this way only when sqrt(s) >= 1024 |delta|max of its bundle
+// (|u| < 0.002: the neglected terms stay below 6e-6 of the pair's ring
+// difference and 1e-8 of the pair term); closer pairs, and pairs within 1e-4
+// Mpc of the expansion point (where s^-7/2 would leave the FP32 range), are
+// left out of the moments and summed per ray directly in FP64.  Softened sets
+// whose softening exceeds 1024 |delta|max for every bundle of a wavefront
+// (boxes: 71 kpc against a few parsecs) skip the nearness test altogether.
+// ===========================================================================
+constexpr int kMom = 20;
+constexpr float kNearRatio2 = 1048576.f;   // (1024)^2
+constexpr float kNearFloor2 = 1e-8f;     // (1e-4 Mpc)^2
+// LDS bytes per wavefront of the FP32 path: its tile, and at least what its
+// share of the moment reduction needs ([20][64] floats, [4][64] doubles, and
+// the group's [20][7] double totals).
+// A tile is TP float4 (x, y in the set's frame, z relative to the stage, m)
+// followed by TP float2 (the rounding residuals of x and y).
+constexpr int kRedBytes = kMom * 64 * 4 + 4 * 64 * 8 + kMom * kSeg * 8;
+template <int TP>
+struct Tile32 {
+  static_assert(TP % 9 == 0, "a tile holds whole rounds of the nine lanes of a bundle");
+  static_assert(TP % 2 == 0, "the residuals start 16-byte aligned");
+  static constexpr int kBytes = (TP * 24 > kRedBytes) ? TP * 24 : kRedBytes;
+  static constexpr int kElems = (kBytes + 15) / 16;
+};
 
-// Four packed particles (three float4) against the lane's ray, unit masses.
-__device__ __forceinline__ void pairs_equal4(const float4* g, float rx, float ry, float rz, float e2, float& p0,
-                                             float& p1, float& p2, float& p3) {
-  const float4 P0 = g[0], P1 = g[1], P2 = g[2];
-  const float px[4] = {P0.x, P0.w, P1.z, P2.y};
-  const float py[4] = {P0.y, P1.x, P1.w, P2.z};
-  const float pz[4] = {P0.z, P1.y, P2.x, P2.w};
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const float ex = px[v] - rx, ey = py[v] - ry, ez = pz[v] - rz;
-    float r2 = fmaf(ex, ex, e2);
-    r2 = fmaf(ey, ey, r2);
-    r2 = fmaf(ez, ez, r2);
-    const float ri = __builtin_amdgcn_rsqf(r2);
-    p0 += ri;
-    const float r3 = ri * ri * ri;
-    p1 = fmaf(r3, ex, p1);
-    p2 = fmaf(r3, ey, p2);
-    p3 = fmaf(r3, ez, p3);
-  }
+// Moment indices.
+enum : int {
+  M_PHI = 0, M_GX, M_GY, M_GZ, M_W, M_VX, M_VY, M_VZ, M_TXX, M_TXY, M_TYY, M_TZX, M_TZY,
+  M_UXXX, M_UXXY, M_UXYY, M_UYYY, M_UZXX, M_UZXY, M_UZYY
+};
+
+// One (bundle, particle) pair.  p = (x, y, z relative to e, m / mref) with x, y
+// still in the set's frame, lo = the residuals of x and y; (ex, ey) = e.  DETECT: return whether the pair is
+// near (s < thr); EXCLUDE: also leave a near pair out of the moments.
+template <bool EQUAL, bool DETECT, bool EXCLUDE>
+__device__ __forceinline__ bool moment_terms(const float4 p, const float2 lo, float ex, float ey, float e2,
+                                             float thr, float (&a)[kMom]) {
+  const float Dx = (p.x - ex) + lo.x, Dy = (p.y - ey) + lo.y, Dz = p.z;
+  float s = fmaf(Dx, Dx, e2);
+  s = fmaf(Dy, Dy, s);
+  s = fmaf(Dz, Dz, s);
+  float ia = __builtin_amdgcn_rsqf(s);
+  const bool near = (DETECT || EXCLUDE) && s < thr;
+  if constexpr (EXCLUDE) ia = near ? 0.f : ia;
+  const float ia2 = ia * ia;
+  const float mia = EQUAL ? ia : p.w * ia;
+  a[M_PHI] += mia;
+  const float w = mia * ia2;
+  a[M_GX] = fmaf(w, Dx, a[M_GX]);
+  a[M_GY] = fmaf(w, Dy, a[M_GY]);
+  a[M_GZ] = fmaf(w, Dz, a[M_GZ]);
+  a[M_W] += w;
+  const float q = w * ia2;
+  const float qx = q * Dx, qy = q * Dy;
+  a[M_VX] += qx;
+  a[M_VY] += qy;
+  a[M_VZ] = fmaf(q, Dz, a[M_VZ]);
+  a[M_TXX] = fmaf(Dx, qx, a[M_TXX]);
+  a[M_TXY] = fmaf(Dx, qy, a[M_TXY]);
+  a[M_TYY] = fmaf(Dy, qy, a[M_TYY]);
+  a[M_TZX] = fmaf(Dz, qx, a[M_TZX]);
+  a[M_TZY] = fmaf(Dz, qy, a[M_TZY]);
+  const float r = q * ia2;
+  const float rx = r * Dx, ry = r * Dy;
+  const float rxx = rx * Dx, rxy = rx * Dy, ryy = ry * Dy;
+  a[M_UXXX] = fmaf(Dx, rxx, a[M_UXXX]);
+  a[M_UXXY] = fmaf(Dx, rxy, a[M_UXXY]);
+  a[M_UXYY] = fmaf(Dx, ryy, a[M_UXYY]);
+  a[M_UYYY] = fmaf(Dy, ryy, a[M_UYYY]);
+  a[M_UZXX] = fmaf(Dz, rxx, a[M_UZXX]);
+  a[M_UZXY] = fmaf(Dz, rxy, a[M_UZXY]);
+  a[M_UZYY] = fmaf(Dz, ryy, a[M_UZYY]);
+  return near;
 }
 
-// Plain FP32 partial sums over one tile, added to the running sums with Kahan
-// compensation.  A set's last tile runs only over its particles (to the next
-// group of four), which is what a set of a few particles costs.
-template <int WPR>
-__device__ __forceinline__ void sum_fp32_equal(const DevSet& s, float4* tile, int q, int lane,
-                                               const float (&A)[kSeg][3], float rx, float ry, float rz, double& S0,
-                                               double& Sx, double& Sy, double& Sz) {
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+// A near pair, summed directly at the ray e + (dx, dy, 0), in FP64 (such pairs
+// are rare).  The nearness test repeats moment_terms' FP32 arithmetic exactly,
+// so the bundle's nine lanes and the lane that left the pair out of the moments
+// agree on every pair.
+// (dz is the ray's height above the staged z: zero in the trace kernel, whose
+// rays share z; points of a field evaluation may differ.)
+template <bool EQUAL>
+__device__ __forceinline__ void near_direct(const float4 p, const float2 lo, float ex, float ey, float e2,
+                                            float thr, float dx, float dy, float dz, double (&d)[4]) {
+  const float Dx = (p.x - ex) + lo.x, Dy = (p.y - ey) + lo.y, Dz = p.z;
+  float s = fmaf(Dx, Dx, e2);
+  s = fmaf(Dy, Dy, s);
+  s = fmaf(Dz, Dz, s);
+  if (!(s < thr)) return;
+  // FP64 from here: the displacement from the particle's two-part position is
+  // exact, and the term's rounding stays far below its ring-minus-anchor difference
+  const double rx = (((double)p.x - ex) + lo.x) - dx, ry = (((double)p.y - ey) + lo.y) - dy;
+  const double rz = (double)Dz - dz;
+  const double s2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, (double)e2)));
+  const double ia = rsqrt_f64(s2);
+  const double mia = EQUAL ? ia : (double)p.w * ia;
+  const double w = mia * ia * ia;
+  d[0] += mia;
+  d[1] += w * rx;
+  d[2] += w * ry;
+  d[3] += w * rz;
+}
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
+  float y = v - c;
+  float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// This wavefront's share of the tiles of one set: Kahan-compensated moments
+// (plain FP32 sums over each tile, then added with compensation) and, for a
+// guarded sum, the near pairs' direct terms of the lane's own ray.  A guarded
+// tile is first summed with the nearness test only; a tile that holds a near
+// pair for some bundle of the wavefront is summed again with those pairs left
+// out, and its near pairs are then added per ray.
+template <bool EQUAL, bool DETECT, bool EXCLUDE>
+__device__ __forceinline__ bool tile_moments(const float4* tile, const float2* tlo, int rounds, int l, float ex,
+                                             float ey, float e2, float thr, float (&a)[kMom]) {
+#pragma unroll
+  for (int k = 0; k < kMom; ++k) a[k] = 0.f;
+  bool any_near = false;
+#pragma unroll 4
+  for (int i = 0; i < rounds; ++i)
+    any_near |= moment_terms<EQUAL, DETECT, EXCLUDE>(tile[9 * i + l], tlo[9 * i + l], ex, ey, e2, thr, a);
+  return any_near;
+}
+
+template <int TP, int WPR, bool EQUAL, bool GUARD>
+__device__ void moment_tiles(const DevSet& s, float4* tile, int q, int lane, float ex, float ey, float thr,
+                             float dx, float dy, float dz, double zrel, float (&ks)[kMom], float (&kc)[kMom],
+                             double (&dir)[4]) {
   const int64_t n = s.n;
   const float e2 = s.eps2f;
-  const int64_t n_chunks = (n + kTile32 - 1) / kTile32;
+  const int l = lane < kLanes ? lane % 9 : 0;
+  const int64_t n_tiles = (n + TP - 1) / TP;
   const float4* __restrict__ src = s.p32;
-  float* tf = reinterpret_cast<float*>(tile);
-  const float4* mine = tile + lane_segment(lane) * kPackedStride;
-  for (int64_t ch = q; ch < n_chunks; ch += WPR) {
-    const int64_t j = ch * kTile32 + lane;
-    // Padding past the end sits so far away that r^2 overflows to +inf, whose
-    // reciprocal square root is +0: it adds exactly nothing.
-    const float4 p = (j < n) ? src[j] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
+  const float4* __restrict__ src_lo = s.p32 + n;
+  float2* tlo = reinterpret_cast<float2*>(tile + TP);
+  for (int64_t ch = q; ch < n_tiles; ch += WPR) {
+    const int64_t base = ch * TP;
+    // Stage: positions in the set's frame (two parts for x and y), z relative
+    // to the stage's z (one FP32 rounding of the exact difference).  Padding
+    // past the end lies so far away that s overflows to +inf, whose reciprocal
+    // square root is +0.
 #pragma unroll
-    for (int b = 0; b < kSeg; ++b) {
-      float* d = tf + 4 * b * kPackedStride + 3 * lane;
-      d[0] = p.x - A[b][0];
-      d[1] = p.y - A[b][1];
-      d[2] = p.z - A[b][2];
+    for (int k = 0; k < (TP + 63) / 64; ++k) {
+      const int j = lane + 64 * k;
+      if (j < TP) {
+        float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+        float2 vl = make_float2(0.f, 0.f);
+        if (base + j < n) {
+          const float4 p = src[base + j], r = src_lo[base + j];
+          v = make_float4(p.x, p.y, (float)(((double)p.z - zrel) + (double)r.z), p.w);
+          vl = make_float2(r.x, r.y);
+        }
+        tile[j] = v;
+        tlo[j] = vl;
+      }
     }
     wave_sync();
-    const int64_t left = n - ch * kTile32;
-    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-    if (left >= kTile32) {
-#pragma unroll
-      for (int u = 0; u < kTile32 / 4; ++u) pairs_equal4(mine + 3 * u, rx, ry, rz, e2, p0, p1, p2, p3);
-    } else {
-      const int groups = (int)((left + 3) / 4);
+    const int64_t left = n - base;
+    // a set's last tile runs only over its particles
+    const int rounds = left >= TP ? TP / 9 : (int)((left + 8) / 9);
+    float a[kMom];
+    const bool near = tile_moments<EQUAL, GUARD, false>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
+    if constexpr (GUARD) {
+      if (__any(near)) {
+        tile_moments<EQUAL, false, true>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
+        const int cnt = left >= TP ? TP : (int)left;
 #pragma unroll 1
-      for (int u = 0; u < groups; ++u) pairs_equal4(mine + 3 * u, rx, ry, rz, e2, p0, p1, p2, p3);
+        for (int j = 0; j < cnt; ++j) near_direct<EQUAL>(tile[j], tlo[j], ex, ey, e2, thr, dx, dy, dz, dir);
+      }
     }
-    kahan_add(s0, c0, p0);
-    kahan_add(s1, c1, p1);
-    kahan_add(s2, c2, p2);
-    kahan_add(s3, c3, p3);
+#pragma unroll
+    for (int k = 0; k < kMom; ++k) kahan_add(ks[k], kc[k], a[k]);
     wave_sync();
   }
-  const double m = s.mass;
-  S0 = m * ((double)s0 - (double)c0);
-  Sx = m * ((double)s1 - (double)c1);
-  Sy = m * ((double)s2 - (double)c2);
-  Sz = m * ((double)s3 - (double)c3);
 }
 
-// One (x, y, z, m) particle against the lane's ray.
-__device__ __forceinline__ void pair_general(const float4 c, float rx, float ry, float rz, float e2, float& p0,
-                                             float& p1, float& p2, float& p3) {
-  const float ex = c.x - rx, ey = c.y - ry, ez = c.z - rz;
-  float r2 = fmaf(ex, ex, e2);
-  r2 = fmaf(ey, ey, r2);
-  r2 = fmaf(ez, ez, r2);
-  const float ri = __builtin_amdgcn_rsqf(r2);
-  const float mr = c.w * ri;
-  p0 += mr;
-  const float mr3 = mr * ri * ri;
-  p1 = fmaf(mr3, ex, p1);
-  p2 = fmaf(mr3, ey, p2);
-  p3 = fmaf(mr3, ez, p3);
-}
+// Field of one set at the lane's ray (FP32 pair terms).  The WPR wavefronts of
+// a group hold the same rays, split the tiles, and meet in LDS (in the group's
+// tiles) in a fixed order, so that every wavefront of the group gets identical
+// results.
+template <int TP, int WPR>
+struct FieldEval32 {
+  static constexpr int kElems = Tile32<TP>::kElems;
 
-// FP32 path.  Each tile of 64 particles is staged once per bundle of the
-// wavefront, as particle - anchor (7 copies); each lane then subtracts only its
-// ray's small offset from its anchor.  The anchor-relative part is rounded
-// identically for the 9 rays of a bundle, so the differences between ring rays
-// and anchor that carry the lensing signal keep full FP32 resolution wherever
-// the bundles are on the sky.
-template <int WPR>
-__device__ __forceinline__ void sum_fp32(const DevSet& s, float4* tile, int q, int lane, const float (&A)[kSeg][3],
-                                         float rx, float ry, float rz, double& S0, double& Sx, double& Sy,
-                                         double& Sz) {
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
-  const int64_t n = s.n;
-  const float e2 = s.eps2f;
-  const int64_t n_chunks = (n + kTile32 - 1) / kTile32;
-  const float4* __restrict__ src = s.p32;
-  const float4* mine = tile + lane_segment(lane) * kCopyStride;
-  for (int64_t ch = q; ch < n_chunks; ch += WPR) {
-    const int64_t j = ch * kTile32 + lane;
-    const float4 p = (j < n) ? src[j] : make_float4(1e15f, 1e15f, 1e15f, 0.f);
+  __device__ static void eval(const DevCosmo& c, const DevSet& s, float4* tile, float4* group, int q, int lane,
+                              double x, double y, double z, double& phi, double& gx, double& gy, double& gz) {
+    // positions in the set's frame (FP64); each bundle's expansion point is its
+    // anchor rounded to FP32; each ray's offset from it in FP32
+    const double X = x - s.org[0], Yv = y - s.org[1], Zl = z - s.org[2];
+    const int seg = lane_segment(lane), anchor = 9 * seg;
+    const float ex = (float)__shfl(X, anchor), ey = (float)__shfl(Yv, anchor);
+    const float dx = (float)(X - (double)ex), dy = (float)(Yv - (double)ey);
+    // Tiles are staged with z relative to one height for the whole wavefront.
+    // The expansion needs every point at that height (always so in the trace
+    // kernel); otherwise every pair is summed directly.
+    const double zrel = __shfl(Zl, 0);
+    const float dz = (float)(Zl - zrel);
+    const bool level = !__any(Zl != zrel);
+    // largest offset in the bundle -> nearness threshold on s
+    const int l = lane < kLanes ? lane % 9 : 0;
+    float m2 = lane < kLanes ? fmaf(dx, dx, dy * dy) : 0.f;
 #pragma unroll
-    for (int b = 0; b < kSeg; ++b)
-      tile[b * kCopyStride + lane] = make_float4(p.x - A[b][0], p.y - A[b][1], p.z - A[b][2], p.w);
-    wave_sync();
-    const int64_t left = n - ch * kTile32;
-    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-    if (left >= kTile32) {
-#pragma unroll
-      for (int u = 0; u < kTile32; ++u) pair_general(mine[u], rx, ry, rz, e2, p0, p1, p2, p3);
-    } else {
-#pragma unroll 1
-      for (int u = 0; u < (int)left; ++u) pair_general(mine[u], rx, ry, rz, e2, p0, p1, p2, p3);
+    for (int off = 1; off < 9; off <<= 1) {
+      const float o = __shfl(m2, (l + off < 9) ? lane + off : lane);
+      m2 = fmaxf(m2, o);
     }
-    kahan_add(s0, c0, p0);
-    kahan_add(s1, c1, p1);
-    kahan_add(s2, c2, p2);
-    kahan_add(s3, c3, p3);
-    wave_sync();
+    m2 = __shfl(m2, anchor);
+    const float thr = level ? fmaxf(kNearRatio2 * m2, kNearFloor2) : __builtin_inff();
+    // Every pair has s >= eps^2: if no bundle's threshold exceeds it, no pair can
+    // be near and the unguarded loop runs.
+    const bool guard = __any(thr > s.eps2f);
+    float ks[kMom], kc[kMom];
+#pragma unroll
+    for (int k = 0; k < kMom; ++k) ks[k] = kc[k] = 0.f;
+    double dir[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool equal = s.equal_mass && *s.equal_mass;
+    if (s.n > 0) {
+      if (equal) {
+        if (guard) moment_tiles<TP, WPR, true, true>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
+        else moment_tiles<TP, WPR, true, false>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
+      } else {
+        if (guard) moment_tiles<TP, WPR, false, true>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
+        else moment_tiles<TP, WPR, false, false>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
+      }
+    }
+    // ---- reduction over the nine lanes of each bundle (and the group's wavefronts)
+    char* area = reinterpret_cast<char*>(group);
+    float* red = reinterpret_cast<float*>(area);                                   // [WPR][20][64]
+    double* dred = reinterpret_cast<double*>(area + WPR * kMom * 64 * 4);          // [WPR][4][64]
+    double* tot = reinterpret_cast<double*>(area + WPR * (kMom * 64 * 4 + 4 * 64 * 8));   // [20][7]
+    if constexpr (WPR > 1) __syncthreads();   // the area spans the group's tiles
+#pragma unroll
+    for (int k = 0; k < kMom; ++k) red[(q * kMom + k) * 64 + lane] = ks[k] - kc[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dred[(q * 4 + k) * 64 + lane] = dir[k];
+    if constexpr (WPR > 1) __syncthreads();
+    else wave_sync();
+    for (int t = q * 64 + lane; t < kMom * kSeg; t += WPR * 64) {
+      const int k = t / kSeg, b = t - k * kSeg;
+      double acc = 0.0;
+#pragma unroll
+      for (int w = 0; w < WPR; ++w)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) acc += (double)red[(w * kMom + k) * 64 + 9 * b + j];
+      tot[t] = acc;
+    }
+    if constexpr (WPR > 1) __syncthreads();
+    else wave_sync();
+    double M[kMom];
+#pragma unroll
+    for (int k = 0; k < kMom; ++k) M[k] = tot[k * kSeg + seg];
+    double D0 = 0.0, D1 = 0.0, D2 = 0.0, D3 = 0.0;
+#pragma unroll
+    for (int w = 0; w < WPR; ++w) {
+      D0 += dred[(w * 4 + 0) * 64 + lane];
+      D1 += dred[(w * 4 + 1) * 64 + lane];
+      D2 += dred[(w * 4 + 2) * 64 + lane];
+      D3 += dred[(w * 4 + 3) * 64 + lane];
+    }
+    if constexpr (WPR > 1) __syncthreads();   // before the tiles are staged again
+    else wave_sync();
+    // ---- the lane's own field from the moments (FP64)
+    const double ddx = dx, ddy = dy;
+    const double d2 = ddx * ddx + ddy * ddy;
+    const double Tx = M[M_TXX] * ddx + M[M_TXY] * ddy;
+    const double Ty = M[M_TXY] * ddx + M[M_TYY] * ddy;
+    const double Tz = M[M_TZX] * ddx + M[M_TZY] * ddy;
+    const double Vd = M[M_VX] * ddx + M[M_VY] * ddy;
+    const double xx = ddx * ddx, xy = 2.0 * ddx * ddy, yy = ddy * ddy;
+    const double Ux = M[M_UXXX] * xx + M[M_UXXY] * xy + M[M_UXYY] * yy;
+    const double Uy = M[M_UXXY] * xx + M[M_UXYY] * xy + M[M_UYYY] * yy;
+    const double Uz = M[M_UZXX] * xx + M[M_UZXY] * xy + M[M_UZYY] * yy;
+    const double W = M[M_W];
+    const double S0 = M[M_PHI] + M[M_GX] * ddx + M[M_GY] * ddy - 0.5 * d2 * W + 1.5 * (ddx * Tx + ddy * Ty) + D0;
+    const double Sx = M[M_GX] + 3.0 * Tx - W * ddx - 1.5 * d2 * M[M_VX] - 3.0 * ddx * Vd + 7.5 * Ux + D1;
+    const double Sy = M[M_GY] + 3.0 * Ty - W * ddy - 1.5 * d2 * M[M_VY] - 3.0 * ddy * Vd + 7.5 * Uy + D2;
+    const double Sz = M[M_GZ] + 3.0 * Tz - 1.5 * d2 * M[M_VZ] + 7.5 * Uz + D3;
+    // the FP32 copy holds masses in units of mref; the equal-mass loop sums unit masses
+    const double gm = -c.G * (equal ? s.mass : s.mref);
+    phi = gm * S0;
+    gx = gm * Sx;
+    gy = gm * Sy;
+    gz = gm * Sz;
+    if (s.background) {
+      double U, ux, uy, uz;
+      cuboid_field(s.lo, s.hi, x, y, z, U, ux, uy, uz);
+      phi += c.G_rho * U;
+      gx += c.G_rho * ux;
+      gy += c.G_rho * uy;
+      gz += c.G_rho * uz;
+    }
   }
-  S0 = (double)s0 - (double)c0;
-  Sx = (double)s1 - (double)c1;
-  Sy = (double)s2 - (double)c2;
-  Sz = (double)s3 - (double)c3;
-}
+};
 
+// ===========================================================================
+// FP64 field sums: the direct sum at each ray, tiles of the caller's FP64
+// particles broadcast to every lane.
+// ===========================================================================
 __device__ __forceinline__ void pair_fp64(const double4 c, double x, double y, double z, double e2, double& a0,
                                           double& a1, double& a2, double& a3) {
   const double ex = c.x - x, ey = c.y - y, ez = c.z - z;
@@ -291,7 +464,6 @@ __device__ __forceinline__ void pair_fp64_unit(const double4 c, double x, double
   a3 = fma(r3, ez, a3);
 }
 
-// FP64 path: tiles of the caller's FP64 particles, broadcast to every lane.
 // UNIT: every mass equals s.mass, which multiplies the finished sums.
 template <int T, int WPR, bool UNIT>
 __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, int lane, double x, double y,
@@ -333,53 +505,22 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, 
   Sz = m * a3;
 }
 
-// LDS needed by one wavefront's tiles.
-template <bool F64, int T>
-struct TileSpace {
-  static constexpr int kElems = F64 ? T : kSeg * kCopyStride;
-  using Elem = typename std::conditional<F64, double4, float4>::type;
-};
-
 // Field of one set at the lane's point for a group of WPR wavefronts holding
 // the same rays: each sums its share of the tiles and the shares meet in LDS
 // in a fixed order, so every wavefront of the group gets identical results.
-template <bool F64, int T, int WPR>
-struct FieldEval {
-  using Tile = typename TileSpace<F64, T>::Elem;
-
-  // red_in_tiles: red lives in the LDS tiles of the workgroup, so every wavefront must have
-  // finished its pair loop before the partial sums are written.
-  __device__ static void eval(const DevCosmo& c, const DevSet& s, Tile* tile, double* red, int q, int lane, double x,
-                              double y, double z, double& phi, double& gx, double& gy, double& gz,
-                              bool red_in_tiles = false) {
+// UNIT selects the loop of sets whose masses are all equal; the caller picks it
+// from the set's device flag.
+template <int T, int WPR>
+struct FieldEval64 {
+  __device__ static void eval(const DevCosmo& c, const DevSet& s, double4* tile, double* red, int q, int lane,
+                              double x, double y, double z, double& phi, double& gx, double& gy, double& gz) {
     double S0, Sx, Sy, Sz;
-    if constexpr (F64) {
-      if (s.equal_mass && *s.equal_mass)
-        sum_fp64<T, WPR, true>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
-      else
-        sum_fp64<T, WPR, false>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
-    } else {
-      // positions in the set's frame (FP64), each bundle's anchor rounded to FP32
-      const double X = x - s.org[0], Yv = y - s.org[1], Z = z - s.org[2];
-      const int anchor = 9 * lane_segment(lane);
-      const double AX = __shfl(X, anchor), AY = __shfl(Yv, anchor), AZ = __shfl(Z, anchor);
-      const float ax = (float)AX, ay = (float)AY, az = (float)AZ;
-      float A[kSeg][3];
-#pragma unroll
-      for (int b = 0; b < kSeg; ++b) {
-        A[b][0] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), 9 * b));
-        A[b][1] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), 9 * b));
-        A[b][2] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), 9 * b));
-      }
-      const float rx = (float)(X - (double)ax), ry = (float)(Yv - (double)ay), rz = (float)(Z - (double)az);
-      if (s.equal_mass && *s.equal_mass)
-        sum_fp32_equal<WPR>(s, tile, q, lane, A, rx, ry, rz, S0, Sx, Sy, Sz);
-      else
-        sum_fp32<WPR>(s, tile, q, lane, A, rx, ry, rz, S0, Sx, Sy, Sz);
-    }
+    if (s.equal_mass && *s.equal_mass)
+      sum_fp64<T, WPR, true>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
+    else
+      sum_fp64<T, WPR, false>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
     if constexpr (WPR > 1) {
       // red: [WPR][4][64] for this group
-      if (red_in_tiles) __syncthreads();
       red[(q * 4 + 0) * 64 + lane] = S0;
       red[(q * 4 + 1) * 64 + lane] = Sx;
       red[(q * 4 + 2) * 64 + lane] = Sy;
@@ -410,55 +551,38 @@ struct FieldEval {
   }
 };
 
-__device__ __forceinline__ void store_state(double* st, int lane, int at, const State& v) {
-  st[(at + 0) * 64 + lane] = v.t;
-  st[(at + 1) * 64 + lane] = v.x;
-  st[(at + 2) * 64 + lane] = v.y;
-  st[(at + 3) * 64 + lane] = v.kt;
-  st[(at + 4) * 64 + lane] = v.kx;
-  st[(at + 5) * 64 + lane] = v.ky;
-  st[(at + 6) * 64 + lane] = v.kz;
-}
-
-__device__ __forceinline__ State load_state(const double* st, int lane, int at) {
-  return State{st[(at + 0) * 64 + lane], st[(at + 1) * 64 + lane], st[(at + 2) * 64 + lane],
-               st[(at + 3) * 64 + lane], st[(at + 4) * 64 + lane], st[(at + 5) * 64 + lane],
-               st[(at + 6) * 64 + lane]};
-}
+// LDS of one precision's field sums, per wavefront.
+template <bool F64, int T>
+struct TileSpace;
+template <int T>
+struct TileSpace<true, T> {
+  using Elem = double4;
+  static constexpr int kElems = T;
+};
+template <int T>
+struct TileSpace<false, T> {
+  using Elem = float4;
+  static constexpr int kElems = Tile32<T>::kElems;
+};
 
 // ---------------------------------------------------------------------------
 // The persistent trace kernel.
 // NW wavefronts per workgroup; WPR of them share 63 rays (7 bundles) and split
-// the particles; T particles per FP64 tile.  Four wavefronts per SIMD are
-// requested: the FP64 state stays in registers through the pair loop, and
-// the compiler spills only inside the rarely used cuboid-background code.
+// the particles; T particles per tile; OCC wavefronts per SIMD requested (the
+// register budget is 512 / OCC per lane).
 // ---------------------------------------------------------------------------
-template <bool F64, int NW, int WPR, int T>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void trace_kernel(TraceParams P) {
+template <bool F64, int NW, int WPR, int T, int OCC>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void trace_kernel(TraceParams P) {
   constexpr int NG = NW / WPR;
-  using FE = FieldEval<F64, T, WPR>;
-  using Tile = typename FE::Tile;
-  // When the WPR wavefronts of a group share rays, one copy of the group's FP64
-  // RK4 state (Y, the stage input and the accumulator: 21 values per ray) waits
-  // in LDS while the field is summed, instead of 128-VGPR wavefronts spilling
-  // their identical copies to scratch.  The reduction buffer then shares the
-  // tiles' LDS, so that the state fits beside them at two workgroups per CU.
-  constexpr int kStateWords = 21 * 64;
-  constexpr int kTileBytes = NW * TileSpace<F64, T>::kElems * (int)sizeof(Tile);
-  // (FP32 path only: the FP64 path measured 4% slower with the extra barriers.)
-  constexpr bool kLdsState = !F64 && WPR >= 2 && kTileBytes + NG * kStateWords * 8 <= 80 * 1024 &&
-                             kTileBytes >= NG * WPR * 4 * 64 * 8;
+  using Tile = typename TileSpace<F64, T>::Elem;
   __shared__ Tile tiles[NW][TileSpace<F64, T>::kElems];
-  __shared__ double red_own[NG][(WPR > 1 && !kLdsState) ? WPR * 4 * 64 : 1];
-  __shared__ double state_lds[kLdsState ? NG : 1][kLdsState ? kStateWords : 1];
+  __shared__ double red_own[NG][(F64 && WPR > 1) ? WPR * 4 * 64 : 1];
   __shared__ int s_item;
 
   // the wavefront index is uniform: keep it (and the tile loop counters) in SGPRs
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = wave / WPR, q = wave % WPR;
   const DevCosmo& cz = P.cosmo;
-  double* red = kLdsState ? reinterpret_cast<double*>(&tiles[0][0]) + g * (WPR * 4 * 64) : &red_own[g][0];
-  double* st = &state_lds[kLdsState ? g : 0][0];
 
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(P.queue, 1);
@@ -492,24 +616,14 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
       for (int stage = 0; stage < 4; ++stage) {
         const double xin = (stage == 0) ? Y.x : Ys.x, yin = (stage == 0) ? Y.y : Ys.y;
         const double zs = (stage == 0) ? Z0 : ((stage == 3) ? Z1 : Z0 + hh);
-        if constexpr (kLdsState) {
-          if (q == 0) {
-            store_state(st, lane, 0, Y);
-            store_state(st, lane, 7, acc);
-            store_state(st, lane, 14, Ys);
-          }
-        }
         double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         if (S >= 0) {
           const DevSet& set = P.sets[f.set_off + S];
-          FE::eval(cz, set, tiles[wave], red, q, lane, xin, yin, zs, phi, gx, gy, gz, kLdsState);
-        }
-        if constexpr (kLdsState) {
-          if (S < 0) __syncthreads();   // the field sum's barriers order the stores otherwise
-          Y = load_state(st, lane, 0);
-          acc = load_state(st, lane, 7);
-          Ys = load_state(st, lane, 14);
-          __syncthreads();              // every wavefront has its copy before the next stores
+          if constexpr (F64)
+            FieldEval64<T, WPR>::eval(cz, set, tiles[wave], &red_own[g][0], q, lane, xin, yin, zs, phi, gx, gy, gz);
+          else
+            FieldEval32<T, WPR>::eval(cz, set, tiles[wave], tiles[g * WPR], q, lane, xin, yin, zs, phi, gx, gy,
+                                      gz);
         }
         const State& Yin = (stage == 0) ? Y : Ys;
         k = rhs(cz, Yin, phi, gx, gy, gz, a);
@@ -558,13 +672,14 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 }
 
 // Field at arbitrary points: one wavefront = 63 points, no particle split.
-// In the FP32 path every group of 9 consecutive points shares the frame of its
-// first point, as the rays of a bundle do in the trace kernel.
+// Every group of 9 consecutive points is treated as a bundle: FP32 sums expand
+// about the first point of the group (rounded to FP32), as the trace kernel
+// does about a bundle's anchor, when the 63 points of the wavefront share z
+// (otherwise each point's sum is direct).
 template <bool F64, int T>
 __global__ __launch_bounds__(256) void field_eval_kernel(DevCosmo c, const DevSet* set_p, int64_t n,
                                                          const double* pts, double* phi, double* grad) {
-  using FE = FieldEval<F64, T, 1>;
-  using Tile = typename FE::Tile;
+  using Tile = typename TileSpace<F64, T>::Elem;
   __shared__ Tile tiles[4][TileSpace<F64, T>::kElems];
   // the wavefront index is uniform: keep it (and the tile loop counters) in SGPRs
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -575,7 +690,12 @@ __global__ __launch_bounds__(256) void field_eval_kernel(DevCosmo c, const DevSe
   if (i >= n) i = n - 1;
   const DevSet set = *set_p;
   double p, gx, gy, gz;
-  FE::eval(c, set, tiles[wave], nullptr, 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx, gy, gz);
+  if constexpr (F64)
+    FieldEval64<T, 1>::eval(c, set, tiles[wave], nullptr, 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx, gy,
+                            gz);
+  else
+    FieldEval32<T, 1>::eval(c, set, tiles[wave], tiles[wave], 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx,
+                            gy, gz);
   if (valid) {
     phi[i] = p;
     grad[i] = gx;
@@ -598,6 +718,7 @@ __global__ void prepare_sets_kernel(DevSet* sets, int32_t n_sets) {
   if (i >= n_sets) return;
   DevSet& s = sets[i];
   s.mass = (s.n > 0) ? s.p64[3 * s.n] : 0.0;
+  s.mref = (s.mass != 0.0 && isfinite(s.mass)) ? s.mass : 1.0;
   if (s.equal_mass) *s.equal_mass = 1;   // cleared by the FP32 conversion at the first other mass
   if (s.background) {
     for (int d = 0; d < 3; ++d) s.org[d] = 0.5 * (s.lo[d] + s.hi[d]);
@@ -608,18 +729,28 @@ __global__ void prepare_sets_kernel(DevSet* sets, int32_t n_sets) {
   }
 }
 
+// The FP32 copy: positions relative to the set's frame origin as an FP32 value
+// and its FP32 rounding residual (so that the FP32 displacement from a ray is
+// rounded once relative to the particle-ray distance, not to the particle's
+// distance from the frame origin), masses in units of the set's first mass (1 if
+// that is 0), which multiplies the finished sums, so that the moments' powers of
+// 1/r stay inside the FP32 range for any mass scale.
 __global__ void convert_set_kernel(const DevSet* set, const double* p64, float4* p32, int64_t n) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const double ox = set->org[0], oy = set->org[1], oz = set->org[2];
   const double m = p64[3 * n + j];
-  if (p32)   // (FP64 sets have no copy: only their masses are checked)
-    p32[j] = make_float4((float)(p64[j] - ox), (float)(p64[n + j] - oy), (float)(p64[2 * n + j] - oz), (float)m);
+  if (p32) {   // (FP64 sets have no copy: only their masses are checked)
+    const double x = p64[j] - ox, y = p64[n + j] - oy, z = p64[2 * n + j] - oz;
+    const float xh = (float)x, yh = (float)y, zh = (float)z;
+    p32[j] = make_float4(xh, yh, zh, (float)(m / set->mref));
+    p32[n + j] = make_float4((float)(x - (double)xh), (float)(y - (double)yh), (float)(z - (double)zh), 0.f);
+  }
   if (!(m == p64[3 * n])) *set->equal_mass = 0;   // (a NaN mass also takes the general path)
 }
 
 // ---------------------------------------------------------------------------
-// Bundle construction (Sec. 2.4, 3.1): one thread per ray.
+// Bundle construction (Sec. 3.1): one thread per ray.
 // ---------------------------------------------------------------------------
 __constant__ double kRingCos[8] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
                                    -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440};
@@ -654,7 +785,7 @@ __global__ void bundles_kernel(DevCosmo c, const double* phi_obs, int64_t b0, in
 }
 
 // ---------------------------------------------------------------------------
-// Bundle reduction (Sec. 2.4, eq. lensmap, magnification): 9 consecutive lanes
+// Bundle reduction (Sec. 3.1, eq. lensmap, magnification): 9 consecutive lanes
 // hold one bundle (7 bundles per wavefront, lane 63 idle); offsets from the
 // anchor and the neighbour's offsets arrive by lane shuffles, and the five
 // sums are reduced within each 9-lane segment.
@@ -811,68 +942,50 @@ __global__ __launch_bounds__(256) void hist_final_kernel(int64_t n, const double
 // Plan table.
 // ---------------------------------------------------------------------------
 struct PlanShape {
-  int nw, wpr, tile;
+  int nw, wpr, tile, occ;
 };
 
-constexpr PlanShape kPlans32[] = {{8, 1, 64}, {8, 2, 64}, {8, 4, 64}, {8, 8, 64}, {4, 1, 64}, {4, 4, 64}};
-constexpr PlanShape kPlans64[] = {{8, 1, 128}, {8, 2, 128}, {8, 4, 128}, {8, 8, 64}, {4, 1, 128}, {4, 4, 128}};
-constexpr int kNumPlans = 6;
+// FP32: tiles of 288 particles (32 rounds of a bundle's nine lanes, 6.9 KB of
+// LDS) at four wavefronts per SIMD (128 registers) or three (168 registers),
+// and tiles of 576 at two (256 registers).
+constexpr PlanShape kPlans32[] = {{8, 1, 288, 4}, {8, 2, 288, 4}, {8, 4, 288, 4}, {8, 8, 288, 4},
+                                  {4, 1, 288, 3}, {4, 4, 288, 3}, {4, 1, 576, 2}, {4, 4, 576, 2}};
+constexpr PlanShape kPlans64[] = {{8, 1, 128, 4}, {8, 2, 128, 4}, {8, 4, 128, 4},
+                                  {8, 8, 64, 4},  {4, 1, 128, 4}, {4, 4, 128, 4}};
+constexpr int kNumPlans32 = sizeof(kPlans32) / sizeof(kPlans32[0]);
+constexpr int kNumPlans64 = sizeof(kPlans64) / sizeof(kPlans64[0]);
 
 template <bool F64, int I>
-struct PlanKernel;
-
-#define RT_PLAN(F64, I, TABLE)                                                                   \
-  template <>                                                                                    \
-  struct PlanKernel<F64, I> {                                                                    \
-    static constexpr PlanShape S = TABLE[I];                                                     \
-    static const void* fn() { return (const void*)&trace_kernel<F64, S.nw, S.wpr, S.tile>; }      \
-    static hipError_t launch(const TraceParams& p, int grid, hipStream_t st) {                  \
-      hipLaunchKernelGGL((trace_kernel<F64, S.nw, S.wpr, S.tile>), dim3(grid), dim3(S.nw * 64), 0, st, p); \
-      return hipGetLastError();                                                                  \
-    }                                                                                            \
-  };
-
-RT_PLAN(false, 0, kPlans32)
-RT_PLAN(false, 1, kPlans32)
-RT_PLAN(false, 2, kPlans32)
-RT_PLAN(false, 3, kPlans32)
-RT_PLAN(false, 4, kPlans32)
-RT_PLAN(false, 5, kPlans32)
-RT_PLAN(true, 0, kPlans64)
-RT_PLAN(true, 1, kPlans64)
-RT_PLAN(true, 2, kPlans64)
-RT_PLAN(true, 3, kPlans64)
-RT_PLAN(true, 4, kPlans64)
-RT_PLAN(true, 5, kPlans64)
-#undef RT_PLAN
-
-template <bool F64>
-const void* plan_fn(int id) {
-  switch (id) {
-    case 0: return PlanKernel<F64, 0>::fn();
-    case 1: return PlanKernel<F64, 1>::fn();
-    case 2: return PlanKernel<F64, 2>::fn();
-    case 3: return PlanKernel<F64, 3>::fn();
-    case 4: return PlanKernel<F64, 4>::fn();
-    default: return PlanKernel<F64, 5>::fn();
+struct PlanKernel {
+  static constexpr PlanShape S = F64 ? kPlans64[I] : kPlans32[I];
+  static const void* fn() { return (const void*)&trace_kernel<F64, S.nw, S.wpr, S.tile, S.occ>; }
+  static hipError_t launch(const TraceParams& p, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((trace_kernel<F64, S.nw, S.wpr, S.tile, S.occ>), dim3(grid), dim3(S.nw * 64), 0, st, p);
+    return hipGetLastError();
   }
+};
+
+template <bool F64, int I = 0>
+const void* plan_fn(int id) {
+  constexpr int n = F64 ? kNumPlans64 : kNumPlans32;
+  if constexpr (I + 1 < n) {
+    if (id != I) return plan_fn<F64, I + 1>(id);
+  }
+  return PlanKernel<F64, I>::fn();
 }
 
-template <bool F64>
+template <bool F64, int I = 0>
 hipError_t plan_launch(int id, const TraceParams& p, int grid, hipStream_t st) {
-  switch (id) {
-    case 0: return PlanKernel<F64, 0>::launch(p, grid, st);
-    case 1: return PlanKernel<F64, 1>::launch(p, grid, st);
-    case 2: return PlanKernel<F64, 2>::launch(p, grid, st);
-    case 3: return PlanKernel<F64, 3>::launch(p, grid, st);
-    case 4: return PlanKernel<F64, 4>::launch(p, grid, st);
-    default: return PlanKernel<F64, 5>::launch(p, grid, st);
+  constexpr int n = F64 ? kNumPlans64 : kNumPlans32;
+  if constexpr (I + 1 < n) {
+    if (id != I) return plan_launch<F64, I + 1>(id, p, grid, st);
   }
+  return PlanKernel<F64, I>::launch(p, grid, st);
 }
 
 }  // namespace
 
-int plan_count(bool) { return kNumPlans; }
+int plan_count(bool fp64) { return fp64 ? kNumPlans64 : kNumPlans32; }
 
 rt_plan_info plan_info(bool fp64, int id) {
   const PlanShape s = fp64 ? kPlans64[id] : kPlans32[id];
@@ -881,6 +994,7 @@ rt_plan_info plan_info(bool fp64, int id) {
   r.waves_per_group = s.wpr;
   r.tile = s.tile;
   r.rays_per_block = kLanes * s.nw / s.wpr;
+  r.waves_per_simd = s.occ;
   return r;
 }
 

@@ -48,7 +48,7 @@ class rt_field(C.Structure):
 
 class rt_plan_info(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("waves_per_group", C.c_int32), ("tile", C.c_int32),
-                ("rays_per_block", C.c_int32)]
+                ("rays_per_block", C.c_int32), ("waves_per_simd", C.c_int32)]
 
 
 class rt_trace_info(C.Structure):

@@ -15,9 +15,9 @@ Workloads (cosmology Omega_m = 0.3, Omega_Lambda = 0.7, h = 0.7 throughout):
   * ``box``: a Zel'dovich-displaced periodic box (100 Mpc/h, P(k) ~ k^-1.5,
     sigma_8 = 0.8), replicated along the line of sight with random periodic
     shifts and 90-degree rotations (Sec. 5.2), 2^18 or 2^20 particles;
-    bundle radius 0.1 arcsec, one of the radii of Sec. 4.2.
+    128 x 128 or 512 x 512 bundles of radius 1e-3 arcsec over 1 deg.
   * ``batched``: 64 uneven fields (point-mass groups, NFW haloes, box
-    sub-volumes), bundle radius 0.1 arcsec.
+    sub-volumes), bundle radius 1e-3 arcsec.
 
 Seeds: master seed 1110; each object draws from its own child of
 ``numpy.random.SeedSequence(seed)``.
@@ -269,7 +269,7 @@ def box_replicas(pos: np.ndarray, box: float, n_rep: int, rng: np.random.Generat
 
 
 def box(n_part_log2: int = 18, n_side: int = 128, z_s: float = 0.5, fov_deg: float = 1.0,
-        radius_arcsec: float = 0.1, n_steps: int = 2000, box_mpc_h: float = 100.0,
+        radius_arcsec: float = 1e-3, n_steps: int = 2000, box_mpc_h: float = 100.0,
         soft_kpc_h: float = 50.0, seed: int = MASTER_SEED, n_replicas: Optional[int] = None) -> Workload:
     cos = Cosmology()
     L = box_mpc_h / cos.h
@@ -329,7 +329,7 @@ def subsample(w: Workload, stride: int, offset: int = 0, max_bundles: Optional[i
 
 # ----------------------------------------------------------------------------- batched uneven fields
 def batched(n_sides=(64, 128, 256), side_override: Optional[int] = None, z_s: float = 0.5,
-            radius_arcsec: float = 0.1, n_fine: int = 500, q: float = 1.1, seed: int = MASTER_SEED,
+            radius_arcsec: float = 1e-3, n_fine: int = 500, q: float = 1.1, seed: int = MASTER_SEED,
             n_point: int = 16, n_nfw: int = 32, n_box: int = 16, nfw_np_range=(10_000, 1_000_000),
             box_sub_mpc_h: float = 25.0) -> Workload:
     """64 independent lens fields of very uneven cost, in this order:

@@ -1,5 +1,5 @@
 """Pins of the oracle's bundle construction, magnification, Jacobian, source-
-weighted PDF (Sec. 2.4, 3.1, 5.3, eq. lensmap, magnification, weighthisto) and of
+weighted PDF (Sec. 3.1, 5.3, eq. lensmap, magnification, weighthisto) and of
 its step schedule."""
 import math
 

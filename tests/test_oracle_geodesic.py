@@ -1,5 +1,5 @@
 """Pins of the oracle's geodesic integration (Sec. 3.2, 3.4, App. A) and of the
-lensing it produces (App. C, Sec. 2.4).
+lensing it produces (App. C, Sec. 3.1).
 
 Christoffel symbols are re-derived symbolically from the metric; the z-form RK4
 is checked against an independent adaptive integrator in the affine parameter,
