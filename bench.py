@@ -1,34 +1,36 @@
 """Benchmark of the ray-bundle lensing hot path on one MI355X.
 
-Workload: the NFW halo (1e5 equal-mass particles from an NFW halo with
-M200 = 1e14 Msun, c = 5, truncated at r200, softening 2 kpc physical, z_l = 0.25,
-z_s = 0.5) with 256 x 256 bundles (anchor + 8 rays, radius 1e-3 arcsec) over
-+-3 r_s and 2000 fine RK4 steps across the halo (2236 steps in all).
+Default workload: the cosmological box with 2^20 particles (a Zel'dovich field
+with P(k) ~ k^-1.5, sigma_8 = 0.8, in a 100 Mpc/h periodic box, replicated 14
+times with random shifts and rotations out to z_s = 0.5), 512 x 512 bundles
+(anchor + 8 ring rays, radius 1e-3 arcsec) over 1 deg x 1 deg, 2000 RK4 steps,
+softening 50 kpc/h; FP32 pair terms with Kahan sums, FP64 integration.
 
-One step = one pass of the whole path over one batch of the bundle grid: a
-band of 7168 consecutive bundles (64 512 rays) of the row-major grid, sized to
-two full rounds of the trace kernel's resident workgroups: bundle
-construction, tracing with FP32 pair terms + Kahan sums and FP64 integration
-(one captured graph with the persistent kernel), magnification and the muPDF.
-Steps walk through the grid band after band.  Inputs (particles, bundle
-directions) are resident in HBM before the timed region.
+One step = one pass of the hot path over one batch: a band of --band bundles
+of the row-major bundle grid advanced through a window of --window RK4 steps
+(rt_trace with a step window, one captured graph per window).  A band's first
+window starts with bundle construction (rt_build_bundles) and its last window
+ends with the magnification (rt_magnification) and the source-weighted muPDF
+(rt_mu_histogram, 200 log bins); with the default 100-step window, 20 steps
+carry one band through the whole schedule.  Steps walk through the windows and
+then through the bands.  Inputs (particles, bundle directions) are resident in
+HBM before the timed region.
 
-Untimed: the bundles of the first timed batch are also traced in FP64 on the
-GPU, to give the mixed-vs-FP64 mu error and the FP64 throughput; the CPU oracle
-is timed on two bundles of the batch (full schedule, all particles).
+Reported beside the timed value (untimed):
+  * mixed vs FP64 on the GPU: a subsample of the first band traced through the
+    whole schedule in both precisions (same bundles, same launch shape): the
+    mu error of the measurement contract (relative for |mu| <= 100, inverse
+    beyond), exit positions, and the FP64 throughput of one full window of the
+    band (the same launch shape as a timed step);
+  * the CPU oracle (FP64, all host threads and one thread) on a bounded sample:
+    a few bundles of the first band through the first window;
+  * the roofline of the trace kernel (HIP events around each launch).
 
-Other workloads (--workload), for the per-workload tables of the design notes:
-point (32 x 32 bundles around a 1e12 Msun point lens, 1225 steps), box18 /
-box20 (Zel'dovich boxes of 2^18 / 2^20 particles in 14 replicas, 0.1 arcsec
-bundles, 2000 steps; one step = one band of --band bundles), batched (64 uneven
-fields traced in one launch, --side x --side bundles per field); and the
-particle-mesh field: nfw_pm (the NFW band through a --pm-n^3 mesh, RK4 in z or,
-with --pm-frk, in the affine parameter), box18_pm / box20_pm (every bundle of the
-box grid through one periodic mesh per replica), pm_study (minimum reliable
-radius of the point lens against mesh resolution and n_int), nfw_study (the NFW
-lens's minimum reliable radius against mesh, n_int, f_RK, bundle radius and
-particle mass, RK4 in the affine parameter), soft_study (the box's muPDF and
-shear PDF at three particle softenings).
+Other workloads (--workload): box18 (2^18 particles, 128 x 128 bundles), nfw
+(1e5-particle NFW halo, 256 x 256 bundles, 2236 steps), point (32 x 32 bundles
+around a 1e12 Msun point lens, 1225 steps), batched (64 uneven fields in one
+launch); the particle-mesh field: nfw_pm, box18_pm / box20_pm; and the
+parameter studies pm_study, nfw_study, soft_study.
 
 Prints one JSON line.
 """
@@ -48,61 +50,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from tests.metrics import mu_stats, mu_gate   # noqa: E402  (statistics only, no oracle)
+
 METRIC = "ray-particle interactions/s and bundles/s at μ err ≤1e-4 vs FP64 (mixed vs FP64)"
 PEAK_FP32 = 157.3      # TFLOP/s, MI355X FP32 vector (published)
 PEAK_FP64 = 78.6       # TFLOP/s, MI355X FP64 vector (published)
-# Algorithmic FLOP per ray-particle interaction: 3 sub, 3 FMA (6), rsqrt (1),
-# m x 1/r (1), 1 add, 2 mul, 3 FMA (6) = 20; 19 for a set of equal masses, whose
-# common mass multiplies the finished sums instead.
-FLOP_PER_INTERACTION = 20.0
-FLOP_PER_INTERACTION_EQUAL_MASS = 19.0
-
-
-def flop_per_interaction(g) -> float:
-    """Interaction-weighted algorithmic FLOP per interaction of a GpuRun's fields."""
-    tot = eq = 0.0
-    for f, spec in zip(g.fields, g.w.fields):
-        equal = [bool(np.all(s.m == s.m[0])) for s in spec.sets]
-        ss = np.asarray(f["step_set"])
-        for j, s in enumerate(spec.sets):
-            n = float(len(s.m)) * f["n_bundles"] * np.count_nonzero(ss == j)
-            tot += n
-            eq += n if equal[j] else 0.0
-    if tot == 0.0:
-        return FLOP_PER_INTERACTION
-    return FLOP_PER_INTERACTION - (FLOP_PER_INTERACTION - FLOP_PER_INTERACTION_EQUAL_MASS) * eq / tot
-# HBM bytes per launch of the FP32 trace kernel on the default workload, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy (factors 2.0 and
-# 1.0), keyed by the sha256 prefix of the kernel sources they were taken with
-# (kernel_source_sha; the first two entries hashed rt_kernels.hip alone).
-MEASURED_TRAFFIC = {"4c91bd822f7f7084": {"read": 791209081351.7532, "write": 309593045824.0},
-                    "22f7c628a65fbf77": {"read": 791358565983.8373, "write": 309592396416.0},
-                    "d9ecd4450456f251": {"read": 791484190955.2822, "write": 309593703488.0},
-                    "4447ca04a41774c8": {"read": 527069855930.1256, "write": 65751117760.0},
-                    # changes only the FP64 instantiations: trace_kernel<false, 8, 8, 64> compiles to the
-                    # same instructions (checked by diffing the gfx950 assembly)
-                    "799090d3d3da2c72": {"read": 527069855930.1256, "write": 65751117760.0},
-                    "ae59e4cd8fd79606": {"read": 438975467239.04016, "write": 28242255520.0},
-                    "88c0e800b45ed36d": {"read": 255562822694.14062, "write": 37611626752.0,
-                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"},
-                    # a comment-only change of the source above: the gfx950 assembly differs only in
-                    # the compilation-unit id symbol
-                    "6aaff9f945547e36": {"read": 255562822694.14062, "write": 37611626752.0,
-                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"},
-                    # the FP64 equal-mass loop: trace_kernel<false, 8, 8, 64> compiles to the same
-                    # gfx950 assembly (diffed)
-                    "209f5451189981e7": {"read": 255562822694.14062, "write": 37611626752.0,
-                                         "summary": "profiles/trace_kernel_fp32_nfw1e5_band7168.md"}}
+# Algorithmic FLOP of the FP32 field sum per (bundle, particle) pair, evaluated once for the
+# bundle's nine rays: displacement from the expansion point with the two-part position (2 sub,
+# 2 add), s = |D|^2 + eps^2 (3 FMA = 6), rsqrt (1), 1/s (1), s^-3/2 (1), potential (1), field
+# (3 FMA = 6), W (1), s^-5/2 (1), its products with Dx, Dy (2), V (2 add, 1 FMA = 4),
+# T (5 FMA = 10), s^-7/2 (1), its products with Dx, Dy (2) and the three second products (3),
+# U (7 FMA = 14): 58; one more (the mass) for sets of unequal masses.
+FLOP_PER_PAIR_EQUAL = 58.0
+FLOP_PER_PAIR = 59.0
+# The direct per-ray pair term (3 sub, 3 FMA, rsqrt, m/r, 1 add, 2 mul, 3 FMA): 20 FLOP per
+# ray-particle interaction.  Reported as the direct-sum equivalent rate.
+FLOP_DIRECT = 20.0
+# FP64 direct sum per ray-particle interaction (same count as the direct term).
+FLOP_FP64 = 20.0
+# HBM bytes per launch of the FP32 trace kernel on the default workload (one 3584-bundle band,
+# one 100-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
+# plain copy kernel, keyed by the sha256 prefix of the kernel sources they were taken with.
+MEASURED_TRAFFIC = {}
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
-    p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="nfw",
-                   choices=["nfw", "point", "box18", "box20", "batched", "nfw_pm", "box18_pm", "box20_pm",
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="box20",
+                   choices=["box20", "box18", "nfw", "point", "batched", "nfw_pm", "box18_pm", "box20_pm",
                             "pm_study", "nfw_study", "soft_study"])
+    p.add_argument("--band", type=int, default=0,
+                   help="bundles per step of the one-field workloads (0: 3584 for box20, 7168 for box18 and nfw)")
+    p.add_argument("--window", type=int, default=-1,
+                   help="RK4 steps per bench step (0: the whole schedule; default 100 for the boxes, 0 otherwise)")
+    p.add_argument("--side", type=int, default=0, help="batched: bundle grid side of every field (0: the "
+                                                       "workload's own seeded 64/128/256)")
+    p.add_argument("--precision", default="fp32k", choices=["fp32k", "fp64"])
+    p.add_argument("--fp64-bundles", type=int, default=0,
+                   help="bundles of the first band traced through the whole schedule in both precisions for the "
+                        "mu error (0: a default per workload)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--cpu-bundles", type=int, default=16)
+    p.add_argument("--plan", type=int, default=-1, help="force a trace plan (skips the autotuner)")
     p.add_argument("--pm-n", type=int, default=256, help="nodes per side of the particle-mesh grid(s)")
     p.add_argument("--pm-compare-stride", type=int, default=0,
                    help="box*_pm: trace every k-th bundle of the grid with the direct sum too (0: 9 for box18, none "
@@ -111,58 +105,28 @@ def parse():
     p.add_argument("--pm-frk", type=float, default=0.0,
                    help="nfw_pm: > 0 integrates in the affine parameter with the step f_RK h / kz_0 (eq. RKstepsize) "
                         "instead of the z nodes")
-    p.add_argument("--band", type=int, default=7168,
-                   help="bundles per step of the single-field workloads (nfw, box18, box20): 7168 bundles = "
-                        "1024 groups of 7 bundles, two full rounds of the 512 workgroups that the trace kernel "
-                        "keeps resident on 256 CUs")
-    p.add_argument("--side", type=int, default=32, help="bundle grid side of each field of the batched workload")
-    p.add_argument("--precision", default="fp32k", choices=["fp32k", "fp64"])
-    p.add_argument("--fp64-stride", type=int, default=1,
-                   help="every k-th bundle of the first timed batch is traced again in FP64")
-    p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-fp64", action="store_true")
-    p.add_argument("--no-autotune", action="store_true")
-    p.add_argument("--cpu-bundles", type=int, default=2)
-    p.add_argument("--plan", type=int, default=-1, help="force a trace plan (skips the autotuner)")
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="only copy a buffer of this many MiB (HBM counter calibration) and exit")
-    return p.parse_args()
+    a = p.parse_args()
+    if a.band == 0:
+        a.band = 3584 if a.workload in ("box20", "box20_pm") else 7168
+    if a.window < 0:
+        a.window = 100 if a.workload in ("box20", "box18") else 0
+    return a
 
 
 def kernel_source_sha() -> str:
-    """sha256 prefix of the trace kernel's code (its kernel file and the shared geodesic header)."""
+    """sha256 prefix of the trace kernel's code (its kernel file and the shared headers)."""
     h = hashlib.sha256()
-    for f in ("rt_kernels.hip", "rt_geodesic.h"):
+    for f in ("rt_kernels.hip", "rt_geodesic.h", "rt_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1110_4894_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
-
-
-def traffic_bytes(a):
-    """Measured HBM bytes per trace launch, or None when the kernel source has changed
-    since the counters were taken or the launch differs from the profiled one."""
-    sha = kernel_source_sha()
-    m = MEASURED_TRAFFIC.get(sha)
-    if m is None or a.workload != "nfw" or a.band != 7168 or a.precision != "fp32k":
-        return None
-    return m["read"] + m["write"]
-
-
-def mu_stats(mu, ref):
-    mu, ref = np.asarray(mu), np.asarray(ref)
-    rel = np.abs(mu - ref) / np.abs(ref)
-    cond = np.abs(mu - ref) / (np.abs(ref) * np.maximum(1.0, np.abs(ref)))
-    weak = np.abs(ref - 1) < 0.5
-    q = lambda a, p: float(np.percentile(a, p)) if a.size else 0.0
-    return {"max_rel": float(rel.max()), "p99_rel": q(rel, 99), "p50_rel": q(rel, 50),
-            "max_rel_weak": float(rel[weak].max()) if weak.any() else 0.0,
-            "max_cond": float(cond.max()), "max_inv_mu": float(np.max(np.abs(1 / mu - 1 / ref))),
-            "n": int(mu.size), "n_weak": int(weak.sum()), "max_abs_mu": float(np.abs(ref).max())}
 
 
 def build_workload(a):
     from paper_1110_4894_amd import workloads
     if a.workload in ("nfw", "nfw_pm"):
-        return workloads.nfw(), ("nfw-halo 1e5 particles (M200 1e14 Msun, c 5, z_l 0.25, z_s 0.5), 256x256 "
+        return workloads.nfw(), ("NFW halo 1e5 particles (M200 1e14 Msun, c 5, z_l 0.25, z_s 0.5), 256x256 "
                                  "bundles over +-3 r_s, r_b 1e-3 arcsec, 2000 fine RK4 steps")
     if a.workload == "point":
         return workloads.schwarzschild(), ("point lens 1e12 Msun at z_l 0.25, z_s 0.5, 32x32 bundles at "
@@ -171,10 +135,12 @@ def build_workload(a):
         n, side = (18, 128) if a.workload.startswith("box18") else (20, 512)
         return workloads.box(n_part_log2=n, n_side=side), (
             "Zel'dovich box 2^%d particles, 100 Mpc/h, 14 replicas to z_s 0.5, %dx%d bundles over 1 deg, "
-            "r_b 0.1 arcsec, 2000 RK4 steps, softening 50 kpc/h" % (n, side, side))
-    return workloads.batched(side_override=a.side), (
+            "r_b 1e-3 arcsec, 2000 RK4 steps, softening 50 kpc/h" % (n, side, side))
+    side = a.side if a.side > 0 else None
+    return workloads.batched(side_override=side), (
         "64 uneven fields (16 point-mass groups, 32 NFW haloes of 1e4-1e6 particles, 16 box sub-volumes), "
-        "%dx%d bundles per field, r_b 0.1 arcsec, 500 fine RK4 steps per field, one launch" % (a.side, a.side))
+        "%s bundles per field, r_b 1e-3 arcsec, 500 fine RK4 steps per field, one launch"
+        % ("%dx%d" % (side, side) if side else "seeded 64^2/128^2/256^2"))
 
 
 def batches(w, a):
@@ -192,6 +158,35 @@ def batches(w, a):
         out.append(workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
                                       [workloads.FieldSpec(f.name, f.sets, th, f.schedule, f.replica_box, {})]))
     return out, band
+
+
+def equal_mass_fraction(g):
+    """Fraction of the (bundle, particle) pairs of a GpuRun whose set has equal masses."""
+    tot = eq = 0.0
+    for f, spec in zip(g.fields, g.w.fields):
+        ss = np.asarray(f["step_set"])
+        for j, s in enumerate(spec.sets):
+            n = float(len(s.m)) * f["n_bundles"] * np.count_nonzero(ss == j)
+            tot += n
+            eq += n if bool(np.all(s.m == s.m[0])) else 0.0
+    return eq / tot if tot else 1.0
+
+
+def exit_errors(r32, r64, theta, radius, chi_s):
+    """Exit-position error relative to the deflection |x - theta chi_s| of each ray (FP64 run)."""
+    nb = theta.shape[1]
+    th = np.repeat(theta, 9, axis=1)
+    ang = np.tile(np.concatenate([[0.0], np.arange(8) * np.pi / 4]), nb)
+    ring = np.tile(np.concatenate([[0.0], np.ones(8)]), nb) * radius
+    thx, thy = th[0] + ring * np.cos(ang), th[1] + ring * np.sin(ang)
+    defl = np.hypot(r64[1] - thx * chi_s, r64[2] - thy * chi_s)
+    dx = np.hypot(r32[1] - r64[1], r32[2] - r64[2])
+    return {"max_rel_deflection": float(np.max(dx / (defl + 1e-12))),
+            "p50_rel_deflection": float(np.median(dx / (defl + 1e-12))), "max_abs_mpc": float(dx.max())}
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -216,7 +211,6 @@ def main():
         print(json.dumps({"copy_bytes": 4 * n}), flush=True)
         return
     rt.load()
-    prec = rt.RT_FP64 if a.precision == "fp64" else rt.RT_FP32_KAHAN
     if a.workload == "nfw_pm":
         return bench_pm(a, torch, rt, workloads, GpuRun, dev)
     if a.workload in ("box18_pm", "box20_pm"):
@@ -227,19 +221,29 @@ def main():
         return bench_nfw_study(a, torch, rt, workloads, dev)
     if a.workload == "soft_study":
         return bench_soft_study(a, torch, rt, workloads, GpuRun, dev)
+    return bench_direct(a, torch, rt, workloads, GpuRun, dev)
 
+
+def bench_direct(a, torch, rt, workloads, GpuRun, dev):
+    prec = rt.RT_FP64 if a.precision == "fp64" else rt.RT_FP32_KAHAN
     t_setup = time.time()
     w, desc = build_workload(a)
-    steps_w, per_step = batches(w, a)
+    bands, per_step = batches(w, a)
     uploads = {}
-    g = GpuRun(steps_w[0], uploads=uploads)
-    thetas = [torch.from_numpy(np.ascontiguousarray(np.concatenate([f.theta for f in sw.fields], axis=1))).to(dev)
-              for sw in steps_w]
+    g = GpuRun(bands[0], uploads=uploads)
+    thetas = [torch.from_numpy(np.ascontiguousarray(np.concatenate([f.theta for f in b.fields], axis=1))).to(dev)
+              for b in bands]
     n_rk = g.max_steps
-    inter_per_step = g.interactions()
+    win = n_rk if a.window <= 0 else min(a.window, n_rk)
+    n_win = -(-n_rk // win)
+    windows = [(k * win, min((k + 1) * win, n_rk)) for k in range(n_win)]
+    inter_win = [g.interactions(s0, s1) for s0, s1 in windows]
+    inter_band = float(sum(inter_win))
     n_part = max(sum(s.xyz.shape[0] for s in f.sets) for f in w.fields)
-    print("setup: %s, %d bundles per step, %d RK4 steps (longest field), %.3e interactions per step (%.1f s)"
-          % (a.workload, per_step, n_rk, inter_per_step, time.time() - t_setup), file=sys.stderr, flush=True)
+    eq = equal_mass_fraction(g)
+    flop_pair = FLOP_PER_PAIR_EQUAL * eq + FLOP_PER_PAIR * (1.0 - eq)
+    say("setup: %s, %d bundles per band, %d RK4 steps in %d windows of %d, %.3e interactions per band (%.1f s)"
+        % (a.workload, per_step, n_rk, n_win, win, inter_band, time.time() - t_setup))
 
     tuned = None
     if a.plan >= 0:
@@ -247,138 +251,203 @@ def main():
         tuned = a.plan
     elif not a.no_autotune:
         g.build_bundles()
-        tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, prec, n_rk // 2, 6, g.n_bundles, g.rays)
-        print("autotune: plan %d %s" % (tuned, rt.rt_plan_describe(prec, tuned)), file=sys.stderr, flush=True)
+        tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, prec, n_rk // 2, min(6, win), g.n_bundles, g.rays)
+        say("autotune: plan %d %s" % (tuned, rt.rt_plan_describe(prec, tuned)))
+
+    pdf = mom = None
 
     def one_step(i):
-        g.set_theta(thetas[i % len(thetas)])
-        g.build_bundles()
-        g.trace(prec)
-        g.magnification()
-        return g.histogram()
+        """Step i: window i % n_win of band i // n_win."""
+        nonlocal pdf, mom
+        b, k = divmod(i, n_win)
+        s0, s1 = windows[k]
+        if k == 0:
+            g.set_theta(thetas[b % len(thetas)])
+            g.build_bundles()
+        g.trace(prec, s0, s1)
+        if k == n_win - 1:
+            g.magnification()
+            pdf, mom = g.histogram()
+        return inter_win[k]
 
     rt.rt_enable_timing(True)
     for i in range(a.warmup):
         one_step(i)
         torch.cuda.synchronize()
-        print("warmup step %d done" % i, file=sys.stderr, flush=True)
+        say("warmup step %d done" % i)
 
-    kernel_ms = []
-    mu_first = None
-    first = a.warmup % len(thetas)
+    kernel_ms, kernel_inter = [], []
+    inter_total = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        one_step(a.warmup + i)
+        n_i = one_step(a.warmup + i)
+        inter_total += n_i
         info = rt.rt_last_trace_info()      # waits for this step's trace graph (events on its stream)
         kernel_ms.append(info["kernel_ms"])
-        if i == 0:
-            mu_first = g.mu.clone()
-            rays_first = g.rays.clone()
-        print("step %d: trace %.1f ms, plan %d, grid %d, items %d, graph reused %d" % (
-            i, info["kernel_ms"], info["plan_id"], info["grid_blocks"], info["n_items"], info["graph_reused"]),
-            file=sys.stderr, flush=True)
+        kernel_inter.append(n_i)
+        say("step %d: window %d, trace %.1f ms, plan %d, grid %d, items %d, graph reused %d" % (
+            i, (a.warmup + i) % n_win, info["kernel_ms"], info["plan_id"], info["grid_blocks"], info["n_items"],
+            info["graph_reused"]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rt.rt_enable_timing(False)
     elapsed = t1 - t0
-    value = inter_per_step * a.steps / elapsed
-    k_ms = float(np.mean(kernel_ms))
-    flop = flop_per_interaction(g)
-    achieved = flop * inter_per_step / (k_ms * 1e-3) / 1e12
-    peak = PEAK_FP64 if prec == rt.RT_FP64 else PEAK_FP32
-    prec_name = "fp64" if prec == rt.RT_FP64 else "fp32-kahan field, fp64 integration"
+    value = inter_total / elapsed
+    inter_per_bundle = inter_band / per_step
+    # roofline of the trace kernel: launches of full windows only (a shorter last window
+    # would weigh the average otherwise)
+    full = [i for i in range(a.steps) if kernel_inter[i] == max(kernel_inter)]
+    k_ms = float(np.mean([kernel_ms[i] for i in full]))
+    inter_launch = max(kernel_inter)
+    pairs_launch = inter_launch / 9.0
+    if prec == rt.RT_FP64:
+        flop_launch, peak = FLOP_FP64 * inter_launch, PEAK_FP64
+    else:
+        flop_launch, peak = flop_pair * pairs_launch, PEAK_FP32
+    achieved = flop_launch / (k_ms * 1e-3) / 1e12
+    sha = kernel_source_sha()
+    m = MEASURED_TRAFFIC.get(sha)
+    traffic = (m["read"] + m["write"]) if (m and a.workload == "box20" and a.band == 3584 and win == 100
+                                           and prec == rt.RT_FP32_KAHAN and m.get("plan") == tuned) else None
+    prec_name = "fp64" if prec == rt.RT_FP64 else "fp32 pair terms with Kahan sums, fp64 integration"
     result = {
         "metric": METRIC, "value": value, "unit": "ray-particle interactions/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == rt.RT_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s (%d RK4 steps in the longest field); one step = %d bundles"
-                               % (desc, n_rk, per_step),
+        "config": {"workload": "%s; one step = %d bundles through a window of %d RK4 steps" % (desc, per_step, win),
                    "name": a.workload, "bundles_per_step": per_step, "rays_per_step": 9 * per_step,
-                   "rk4_steps": n_rk, "particles": n_part, "precision": prec_name,
+                   "rk4_steps": n_rk, "window": win, "particles": n_part, "precision": prec_name,
                    "parallelism": "single GPU", "plan": tuned},
-        "bundles_per_s": per_step * a.steps / elapsed,
-        "interactions_per_step": inter_per_step,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic_bytes(a),
-                     "traffic_unit": "HBM bytes per launch (read + write)",
+        "bundles_per_s": value / inter_per_bundle,
+        "interactions_per_bundle": inter_per_bundle,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (read + write)",
                      "kernel": "trace_kernel (%s)" % ("fp64" if prec == rt.RT_FP64 else "fp32"),
-                     "kernel_ms": k_ms, "flop_per_interaction": flop},
+                     "kernel_ms": k_ms, "launch_interactions": inter_launch,
+                     "flop_per_unit": FLOP_FP64 if prec == rt.RT_FP64 else flop_pair,
+                     "unit_of_work": "ray-particle interaction" if prec == rt.RT_FP64
+                     else "(bundle, particle) pair at one RK4 stage (9 rays)",
+                     "direct_equiv_tflops": FLOP_DIRECT * inter_launch / (k_ms * 1e-3) / 1e12},
     }
+    if mom is not None:
+        mo = mom.cpu().numpy()
+        result["mupdf_last_band"] = {"sum_w": float(mo[0]), "mean_mu_w": float(mo[1]), "sigma_mu_w": float(mo[2]),
+                                     "n_mu_le_0": int(mo[3]), "n_below": int(mo[4]), "n_above": int(mo[5])}
+    say("timed: %.4e interactions/s, %.2f bundles/s, trace kernel %.1f ms per window, %.1f TFLOP/s"
+        % (value, result["bundles_per_s"], k_ms, achieved))
 
-    # ---------------------------------------------------------------- FP64 reference on the first batch
+    # ---------------------------------------------------------------- mixed vs FP64 on the same bundles
     if not a.no_fp64 and prec != rt.RT_FP64:
-        sw = steps_w[first]
-        sub = [workloads.FieldSpec(f.name, f.sets, np.ascontiguousarray(f.theta[:, ::a.fp64_stride]),
-                                   f.schedule, f.replica_box, {}) for f in sw.fields]
-        gs = GpuRun(workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius, sub), uploads=uploads)
-        gs.build_bundles()
+        b0 = bands[0]
+        nf = a.fp64_bundles or {"box20": 126, "box18": 504, "nfw": 7168, "point": 1024}.get(a.workload, 0)
+        if a.workload == "batched":
+            sub = b0
+        else:
+            f = b0.fields[0]
+            stride = max(1, f.n_bundles // nf)
+            sub = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
+                                     [workloads.FieldSpec(f.name, f.sets,
+                                                          np.ascontiguousarray(f.theta[:, ::stride][:, :nf]),
+                                                          f.schedule, f.replica_box, {})])
+        gs = GpuRun(sub, uploads=uploads)
+        outs = {}
+        for p_ in (rt.RT_FP32_KAHAN, rt.RT_FP64):
+            gs.build_bundles()
+            rt.rt_enable_timing(True)
+            gs.trace(p_)
+            info = rt.rt_last_trace_info()
+            rt.rt_enable_timing(False)
+            gs.magnification()
+            torch.cuda.synchronize()
+            outs[p_] = (gs.mu.cpu().numpy().copy(), gs.rays.cpu().numpy().copy(), info["kernel_ms"])
+            say("gpu %s on %d bundles: %.1f ms" % ("fp64" if p_ == rt.RT_FP64 else "fp32", gs.n_bundles,
+                                                    info["kernel_ms"]))
+        m32, r32, ms32 = outs[rt.RT_FP32_KAHAN]
+        m64, r64, ms64 = outs[rt.RT_FP64]
+        st = mu_stats(m32, m64)
+        st["gate_1e-4"] = mu_gate(m32, m64, 1e-4)
+        st["bundles"] = "%d bundles of the first band (every %s-th), whole schedule, both precisions on the GPU" % (
+            m64.size, "" if a.workload == "batched" else str(max(1, bands[0].fields[0].n_bundles // max(nf, 1))))
+        result["mu_err_vs_fp64"] = st
+        theta_sub = np.concatenate([f.theta for f in sub.fields], axis=1)
+        result["exit_err_vs_fp64"] = exit_errors(r32, r64, theta_sub, w.bundle_radius, gs.chi_s)
+        fp64 = {"subsample_mixed_ms": ms32, "subsample_fp64_ms": ms64}
+        # FP64 throughput at the timed launch shape: one full window of the first band
+        g.set_theta(thetas[0])
+        g.build_bundles()
+        s0, s1 = windows[0]
         rt.rt_enable_timing(True)
-        gs.trace(rt.RT_FP64)
+        g.trace(rt.RT_FP64, s0, s1)
         info = rt.rt_last_trace_info()
         rt.rt_enable_timing(False)
-        gs.magnification()
-        torch.cuda.synchronize()
-        off = np.cumsum([0] + [f.n_bundles for f in sw.fields])
-        m_all = mu_first.cpu().numpy()
-        m32 = np.concatenate([m_all[o:o + f.n_bundles][::a.fp64_stride] for o, f in zip(off, sw.fields)])
-        m64 = gs.mu.cpu().numpy()
-        result["mu_err_vs_fp64"] = mu_stats(m32, m64)
-        # exit positions: |dx| relative to the deflection |x - theta chi_s| of the FP64 run
-        bidx = np.concatenate([o + np.arange(f.n_bundles)[::a.fp64_stride] for o, f in zip(off, sw.fields)])
-        ridx = (9 * bidx[:, None] + np.arange(9)).ravel()
-        r32 = rays_first.cpu().numpy()[:, ridx]
-        r64 = gs.rays.cpu().numpy()
-        th = np.repeat(np.concatenate([f.theta[:, ::a.fp64_stride] for f in sw.fields], axis=1), 9, axis=1)
-        ang = np.tile(np.concatenate([[0.0], np.arange(8) * np.pi / 4]), bidx.size)
-        ring = np.tile(np.concatenate([[0.0], np.ones(8)]), bidx.size) * w.bundle_radius
-        thx, thy = th[0] + ring * np.cos(ang), th[1] + ring * np.sin(ang)
-        defl = np.hypot(r64[1] - thx * gs.chi_s, r64[2] - thy * gs.chi_s)
-        dx = np.hypot(r32[1] - r64[1], r32[2] - r64[2])
-        result["exit_err_vs_fp64"] = {"max_rel_deflection": float(np.max(dx / (defl + 1e-12))),
-                                      "p50_rel_deflection": float(np.median(dx / (defl + 1e-12))),
-                                      "max_abs_mpc": float(dx.max())}
-        rate64 = gs.interactions() / (info["kernel_ms"] * 1e-3)
-        result["fp64"] = {"interactions_per_s": rate64, "bundles": int(m64.size), "kernel_ms": info["kernel_ms"],
-                          "tflops": flop * rate64 / 1e12,
-                          "frac_of_fp64_peak": flop * rate64 / 1e12 / PEAK_FP64,
-                          "mixed_speedup": (inter_per_step / (k_ms * 1e-3)) / rate64}
-        print("fp64 reference: %s" % json.dumps(result["mu_err_vs_fp64"]), file=sys.stderr, flush=True)
+        rate64 = inter_win[0] / (info["kernel_ms"] * 1e-3)
+        rate32 = inter_launch / (k_ms * 1e-3)
+        fp64.update({"interactions_per_s": rate64, "kernel_ms": info["kernel_ms"],
+                     "shape": "%d bundles, RK4 steps [%d, %d)" % (per_step, s0, s1),
+                     "tflops": FLOP_FP64 * rate64 / 1e12, "frac_of_fp64_peak": FLOP_FP64 * rate64 / 1e12 / PEAK_FP64,
+                     "mixed_speedup": rate32 / rate64})
+        result["fp64"] = fp64
+        say("fp64: %s; mu err %s" % (json.dumps(fp64), json.dumps(st)))
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
-        import oracle as orc
-        from tests.oracle_run import oracle_fields
-        sw = steps_w[first]
+        result["cpu_baseline"] = cpu_baseline(a, w, bands[0], windows[0], workloads)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(a, w, band, window, workloads):
+    """The FP64 oracle on a bounded sample of the first band: a few bundles through the first
+    window of the schedule, on all host threads (as many bundles as threads, nine rays each),
+    and one bundle on one thread."""
+    import oracle as orc
+    from tests.oracle_run import oracle_fields
+    s0, s1 = window
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+
+    def run(nb, n_threads, steps):
         if a.workload == "batched":
-            # one bundle from each of the cheapest fields
-            cost = [sum(s.xyz.shape[0] for s in f.sets) for f in sw.fields]
-            pick = sorted(range(len(sw.fields)), key=lambda i: cost[i])[: 3 * a.cpu_bundles]
-            fields = [workloads.FieldSpec(sw.fields[i].name, sw.fields[i].sets,
-                                          np.ascontiguousarray(sw.fields[i].theta[:, :1]), sw.fields[i].schedule,
-                                          sw.fields[i].replica_box, {}) for i in pick]
+            cost = [sum(s.xyz.shape[0] for s in f.sets) for f in band.fields]
+            pick = sorted(range(len(band.fields)), key=lambda i: -cost[i])[:nb]
+            fields = [workloads.FieldSpec(band.fields[i].name, band.fields[i].sets,
+                                          np.ascontiguousarray(band.fields[i].theta[:, :1]), band.fields[i].schedule,
+                                          band.fields[i].replica_box, {}) for i in pick]
         else:
-            f = sw.fields[0]
-            fields = [workloads.FieldSpec(f.name, f.sets,
-                                          np.ascontiguousarray(f.theta[:, ::37][:, :a.cpu_bundles]),
+            f = band.fields[0]
+            stride = max(1, f.n_bundles // nb)
+            fields = [workloads.FieldSpec(f.name, f.sets, np.ascontiguousarray(f.theta[:, ::stride][:, :nb]),
                                           f.schedule, f.replica_box, {})]
         ws = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius, fields)
         c, chi_s, ofields, theta = oracle_fields(ws)
         rays = orc.build_bundles(c, ofields, theta, ws.bundle_radius)
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-        tc0 = time.perf_counter()
-        orc.trace(c, ofields, rays, n_threads=threads)
-        tc = time.perf_counter() - tc0
+        t0 = time.perf_counter()
+        orc.trace(c, ofields, rays, s0, s0 + steps, n_threads=n_threads)
+        dt = time.perf_counter() - t0
         n_inter = 0.0
         for of in ofields:
-            npart = np.array([len(of.sets[s].m) if s >= 0 else 0 for s in of.step_set], dtype=np.float64)
+            ss = of.step_set[s0:s0 + steps]
+            npart = np.array([len(of.sets[s].m) if s >= 0 else 0 for s in ss], dtype=np.float64)
             n_inter += 9.0 * of.n_bundles * 4.0 * npart.sum()
-        result["cpu_baseline"] = {"value": n_inter / tc, "unit": "ray-particle interactions/s", "cores": threads,
-                                  "kind": "oracle", "seconds": tc,
-                                  "sample": "%d bundles (%d rays) of the first timed batch, full schedules and "
-                                            "particle sets, FP64" % (ws.n_bundles, 9 * ws.n_bundles)}
-    print(json.dumps(result), flush=True)
+        return n_inter, dt, ws.n_bundles
+
+    # size the sample from a short single-thread probe so that each leg takes ~10-20 s
+    probe_steps = max(1, min(s1 - s0, 4))
+    n1, d1, _ = run(1, 1, probe_steps)
+    rate1 = n1 / d1
+    per_step_1 = n1 / probe_steps
+    steps1 = int(max(1, min(s1 - s0, 12.0 * rate1 / per_step_1)))
+    n1, d1, _ = run(1, 1, steps1)
+    nb = max(threads, a.cpu_bundles) if a.workload != "batched" else min(threads, 8)
+    steps_n = int(max(1, min(s1 - s0, 15.0 * rate1 * threads / (per_step_1 * nb))))
+    nn, dn, nbn = run(nb, threads, steps_n)
+    say("cpu oracle: %d threads %.3e interactions/s (%d bundles x %d steps, %.1f s); 1 thread %.3e (%d steps, %.1f s)"
+        % (threads, nn / dn, nbn, steps_n, dn, n1 / d1, steps1, d1))
+    return {"value": nn / dn, "unit": "ray-particle interactions/s", "cores": threads, "kind": "oracle",
+            "seconds": dn, "single_thread": n1 / d1, "single_thread_seconds": d1,
+            "sample": "%d bundles (%d rays) of the first band through RK4 steps [%d, %d) with all particles, FP64, "
+                      "%d threads; single thread: 1 bundle through [%d, %d)"
+                      % (nbn, 9 * nbn, s0, s0 + steps_n, threads, s0, s0 + steps1)}
 
 
 def bench_pm(a, torch, rt, workloads, GpuRun, dev):

@@ -146,15 +146,32 @@ constexpr float kNearFloor2 = 1e-8f;     // (1e-4 Mpc)^2
 // LDS bytes per wavefront of the FP32 path: its tile, and at least what its
 // share of the moment reduction needs ([20][64] floats, [4][64] doubles, and
 // the group's [20][7] double totals).
-// A tile is TP float4 (x, y in the set's frame, z relative to the stage, m)
-// followed by TP float2 (the rounding residuals of x and y).
+// LDS of the FP32 path, per workgroup: WPR tiles (one per wavefront index q of
+// the ray groups; the NG groups of a workgroup share them), each TP float4
+// (x, y in the set's frame, z relative to the stage, m) followed by TP float2
+// (the rounding residuals of x and y).  After the last tile the same bytes hold
+// the moment reduction: per wavefront [20][64] floats, [4][64] doubles and, per
+// group, [20][7] double totals.
 constexpr int kRedBytes = kMom * 64 * 4 + 4 * 64 * 8 + kMom * kSeg * 8;
-template <int TP>
-struct Tile32 {
+static_assert(kRedBytes % 16 == 0, "reduction areas stay 16-byte aligned");
+template <int NW, int WPR, int TP>
+struct Lds32 {
   static_assert(TP % 9 == 0, "a tile holds whole rounds of the nine lanes of a bundle");
   static_assert(TP % 2 == 0, "the residuals start 16-byte aligned");
-  static constexpr int kBytes = (TP * 24 > kRedBytes) ? TP * 24 : kRedBytes;
-  static constexpr int kElems = (kBytes + 15) / 16;
+  static constexpr int kTileElems = TP * 24 / 16;                    // float4 per tile
+  static constexpr int kTileBytes = WPR * TP * 24;
+  static constexpr int kRed = NW * kRedBytes;
+  static constexpr int kElems = ((kTileBytes > kRed) ? kTileBytes : kRed) / 16;
+};
+
+// LDS elements of a kernel's FP32 workgroup tiles (none for FP64 kernels).
+template <bool F64, int NW, int WPR, int TP>
+struct Lds32Elems {
+  static constexpr int v = 1;
+};
+template <int NW, int WPR, int TP>
+struct Lds32Elems<false, NW, WPR, TP> {
+  static constexpr int v = Lds32<NW, WPR, TP>::kElems;
 };
 
 // Moment indices.
@@ -260,80 +277,98 @@ __device__ __forceinline__ bool tile_moments(const float4* tile, const float2* t
   return any_near;
 }
 
-template <int TP, int WPR, bool EQUAL, bool GUARD>
-__device__ void moment_tiles(const DevSet& s, float4* tile, int q, int lane, float ex, float ey, float thr,
+// The tiles of one set, walked by all wavefronts of the workgroup in the same
+// number of rounds: in round it, the NG wavefronts of index q stage tile
+// q + it WPR together and each sums it for its own bundles.
+template <int TP, int WPR, int NG, bool EQUAL, bool GUARD>
+__device__ void moment_tiles(const DevSet& s, float4* tile, int q, int g, int lane, float ex, float ey, float thr,
                              float dx, float dy, float dz, double zrel, float (&ks)[kMom], float (&kc)[kMom],
                              double (&dir)[4]) {
   const int64_t n = s.n;
   const float e2 = s.eps2f;
   const int l = lane < kLanes ? lane % 9 : 0;
   const int64_t n_tiles = (n + TP - 1) / TP;
+  const int64_t n_rounds = (n_tiles + WPR - 1) / WPR;
   const float4* __restrict__ src = s.p32;
   const float4* __restrict__ src_lo = s.p32 + n;
   float2* tlo = reinterpret_cast<float2*>(tile + TP);
-  for (int64_t ch = q; ch < n_tiles; ch += WPR) {
+  // the stage's z in two FP32 parts
+  const float zr_hi = (float)zrel, zr_lo = (float)(zrel - (double)zr_hi);
+  for (int64_t it = 0; it < n_rounds; ++it) {
+    const int64_t ch = q + it * WPR;
     const int64_t base = ch * TP;
     // Stage: positions in the set's frame (two parts for x and y), z relative
-    // to the stage's z (one FP32 rounding of the exact difference).  Padding
-    // past the end lies so far away that s overflows to +inf, whose reciprocal
-    // square root is +0.
+    // to the stage's z.  Padding past the end lies so far away that s
+    // overflows to +inf, whose reciprocal square root is +0.
+    if (ch < n_tiles) {
 #pragma unroll
-    for (int k = 0; k < (TP + 63) / 64; ++k) {
-      const int j = lane + 64 * k;
-      if (j < TP) {
-        float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-        float2 vl = make_float2(0.f, 0.f);
-        if (base + j < n) {
-          const float4 p = src[base + j], r = src_lo[base + j];
-          v = make_float4(p.x, p.y, (float)(((double)p.z - zrel) + (double)r.z), p.w);
-          vl = make_float2(r.x, r.y);
+      for (int k = 0; k < (TP + NG * 64 - 1) / (NG * 64); ++k) {
+        const int j = g * 64 + lane + NG * 64 * k;
+        if (j < TP) {
+          float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+          float2 vl = make_float2(0.f, 0.f);
+          if (base + j < n) {
+            const float4 p = src[base + j], r = src_lo[base + j];
+            v = make_float4(p.x, p.y, (p.z - zr_hi) + (r.z - zr_lo), p.w);
+            vl = make_float2(r.x, r.y);
+          }
+          tile[j] = v;
+          tlo[j] = vl;
         }
-        tile[j] = v;
-        tlo[j] = vl;
       }
     }
-    wave_sync();
-    const int64_t left = n - base;
-    // a set's last tile runs only over its particles
-    const int rounds = left >= TP ? TP / 9 : (int)((left + 8) / 9);
-    float a[kMom];
-    const bool near = tile_moments<EQUAL, GUARD, false>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
-    if constexpr (GUARD) {
-      if (__any(near)) {
-        tile_moments<EQUAL, false, true>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
-        const int cnt = left >= TP ? TP : (int)left;
+    __syncthreads();
+    if (ch < n_tiles) {
+      const int64_t left = n - base;
+      // a set's last tile runs only over its particles
+      const int rounds = left >= TP ? TP / 9 : (int)((left + 8) / 9);
+      float a[kMom];
+      const bool near = tile_moments<EQUAL, GUARD, false>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
+      if constexpr (GUARD) {
+        if (__any(near)) {
+          tile_moments<EQUAL, false, true>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
+          const int cnt = left >= TP ? TP : (int)left;
 #pragma unroll 1
-        for (int j = 0; j < cnt; ++j) near_direct<EQUAL>(tile[j], tlo[j], ex, ey, e2, thr, dx, dy, dz, dir);
+          for (int j = 0; j < cnt; ++j) near_direct<EQUAL>(tile[j], tlo[j], ex, ey, e2, thr, dx, dy, dz, dir);
+        }
       }
-    }
 #pragma unroll
-    for (int k = 0; k < kMom; ++k) kahan_add(ks[k], kc[k], a[k]);
-    wave_sync();
+      for (int k = 0; k < kMom; ++k) kahan_add(ks[k], kc[k], a[k]);
+    }
+    __syncthreads();   // before the tile is staged again
   }
 }
 
 // Field of one set at the lane's ray (FP32 pair terms).  The WPR wavefronts of
-// a group hold the same rays, split the tiles, and meet in LDS (in the group's
-// tiles) in a fixed order, so that every wavefront of the group gets identical
-// results.
-template <int TP, int WPR>
+// a group hold the same rays and split the tiles; all wavefronts of the
+// workgroup share the staged tiles.  The group's partial moments meet in LDS
+// in a fixed order, so that every wavefront of the group gets identical
+// results.  Every wavefront of the workgroup must call this for the same set.
+template <int NW, int WPR, int TP>
 struct FieldEval32 {
-  static constexpr int kElems = Tile32<TP>::kElems;
+  static constexpr int NG = NW / WPR;
+  using L = Lds32<NW, WPR, TP>;
 
-  __device__ static void eval(const DevCosmo& c, const DevSet& s, float4* tile, float4* group, int q, int lane,
-                              double x, double y, double z, double& phi, double& gx, double& gy, double& gz) {
+  __device__ static void eval(const DevCosmo& c, const DevSet& s, float4* lds, int g, int q, int lane, double x,
+                              double y, double z, double& phi, double& gx, double& gy, double& gz) {
     // positions in the set's frame (FP64); each bundle's expansion point is its
     // anchor rounded to FP32; each ray's offset from it in FP32
     const double X = x - s.org[0], Yv = y - s.org[1], Zl = z - s.org[2];
     const int seg = lane_segment(lane), anchor = 9 * seg;
     const float ex = (float)__shfl(X, anchor), ey = (float)__shfl(Yv, anchor);
     const float dx = (float)(X - (double)ex), dy = (float)(Yv - (double)ey);
-    // Tiles are staged with z relative to one height for the whole wavefront.
+    // Tiles are staged with z relative to one height for the whole workgroup.
     // The expansion needs every point at that height (always so in the trace
-    // kernel); otherwise every pair is summed directly.
+    // kernel, whose work items are rays of one field); a wavefront with other
+    // heights sums every pair directly.
     const double zrel = __shfl(Zl, 0);
-    const float dz = (float)(Zl - zrel);
-    const bool level = !__any(Zl != zrel);
+    __shared__ double zshared;
+    if (threadIdx.x == 0) zshared = zrel;
+    __syncthreads();
+    const double zwg = zshared;
+    __syncthreads();
+    const float dz = (float)(Zl - zwg);
+    const bool level = !__any(Zl != zwg);
     // largest offset in the bundle -> nearness threshold on s
     const int l = lane < kLanes ? lane % 9 : 0;
     float m2 = lane < kLanes ? fmaf(dx, dx, dy * dy) : 0.f;
@@ -352,27 +387,27 @@ struct FieldEval32 {
     for (int k = 0; k < kMom; ++k) ks[k] = kc[k] = 0.f;
     double dir[4] = {0.0, 0.0, 0.0, 0.0};
     const bool equal = s.equal_mass && *s.equal_mass;
+    float4* tile = lds + q * L::kTileElems;
     if (s.n > 0) {
       if (equal) {
-        if (guard) moment_tiles<TP, WPR, true, true>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
-        else moment_tiles<TP, WPR, true, false>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
+        if (guard) moment_tiles<TP, WPR, NG, true, true>(s, tile, q, g, lane, ex, ey, thr, dx, dy, dz, zwg, ks, kc, dir);
+        else moment_tiles<TP, WPR, NG, true, false>(s, tile, q, g, lane, ex, ey, thr, dx, dy, dz, zwg, ks, kc, dir);
       } else {
-        if (guard) moment_tiles<TP, WPR, false, true>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
-        else moment_tiles<TP, WPR, false, false>(s, tile, q, lane, ex, ey, thr, dx, dy, dz, zrel, ks, kc, dir);
+        if (guard) moment_tiles<TP, WPR, NG, false, true>(s, tile, q, g, lane, ex, ey, thr, dx, dy, dz, zwg, ks, kc, dir);
+        else moment_tiles<TP, WPR, NG, false, false>(s, tile, q, g, lane, ex, ey, thr, dx, dy, dz, zwg, ks, kc, dir);
       }
     }
-    // ---- reduction over the nine lanes of each bundle (and the group's wavefronts)
-    char* area = reinterpret_cast<char*>(group);
+    // ---- reduction over the nine lanes of each bundle and the group's wavefronts
+    // (the tiles are free: moment_tiles ends with a barrier)
+    char* area = reinterpret_cast<char*>(lds) + g * WPR * kRedBytes;
     float* red = reinterpret_cast<float*>(area);                                   // [WPR][20][64]
     double* dred = reinterpret_cast<double*>(area + WPR * kMom * 64 * 4);          // [WPR][4][64]
     double* tot = reinterpret_cast<double*>(area + WPR * (kMom * 64 * 4 + 4 * 64 * 8));   // [20][7]
-    if constexpr (WPR > 1) __syncthreads();   // the area spans the group's tiles
 #pragma unroll
     for (int k = 0; k < kMom; ++k) red[(q * kMom + k) * 64 + lane] = ks[k] - kc[k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) dred[(q * 4 + k) * 64 + lane] = dir[k];
-    if constexpr (WPR > 1) __syncthreads();
-    else wave_sync();
+    __syncthreads();
     for (int t = q * 64 + lane; t < kMom * kSeg; t += WPR * 64) {
       const int k = t / kSeg, b = t - k * kSeg;
       double acc = 0.0;
@@ -382,8 +417,7 @@ struct FieldEval32 {
         for (int j = 0; j < 9; ++j) acc += (double)red[(w * kMom + k) * 64 + 9 * b + j];
       tot[t] = acc;
     }
-    if constexpr (WPR > 1) __syncthreads();
-    else wave_sync();
+    __syncthreads();
     double M[kMom];
 #pragma unroll
     for (int k = 0; k < kMom; ++k) M[k] = tot[k * kSeg + seg];
@@ -395,8 +429,7 @@ struct FieldEval32 {
       D2 += dred[(w * 4 + 2) * 64 + lane];
       D3 += dred[(w * 4 + 3) * 64 + lane];
     }
-    if constexpr (WPR > 1) __syncthreads();   // before the tiles are staged again
-    else wave_sync();
+    __syncthreads();   // before the tiles are staged again
     // ---- the lane's own field from the moments (FP64)
     const double ddx = dx, ddy = dy;
     const double d2 = ddx * ddx + ddy * ddy;
@@ -551,20 +584,6 @@ struct FieldEval64 {
   }
 };
 
-// LDS of one precision's field sums, per wavefront.
-template <bool F64, int T>
-struct TileSpace;
-template <int T>
-struct TileSpace<true, T> {
-  using Elem = double4;
-  static constexpr int kElems = T;
-};
-template <int T>
-struct TileSpace<false, T> {
-  using Elem = float4;
-  static constexpr int kElems = Tile32<T>::kElems;
-};
-
 // ---------------------------------------------------------------------------
 // The persistent trace kernel.
 // NW wavefronts per workgroup; WPR of them share 63 rays (7 bundles) and split
@@ -574,9 +593,10 @@ struct TileSpace<false, T> {
 template <bool F64, int NW, int WPR, int T, int OCC>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void trace_kernel(TraceParams P) {
   constexpr int NG = NW / WPR;
-  using Tile = typename TileSpace<F64, T>::Elem;
-  __shared__ Tile tiles[NW][TileSpace<F64, T>::kElems];
+  // FP64: a tile per wavefront; FP32: workgroup tiles (Lds32)
+  __shared__ double4 tiles64[F64 ? NW : 1][F64 ? T : 1];
   __shared__ double red_own[NG][(F64 && WPR > 1) ? WPR * 4 * 64 : 1];
+  __shared__ float4 lds32[Lds32Elems<F64, NW, WPR, T>::v];
   __shared__ int s_item;
 
   // the wavefront index is uniform: keep it (and the tile loop counters) in SGPRs
@@ -620,10 +640,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC, OC
         if (S >= 0) {
           const DevSet& set = P.sets[f.set_off + S];
           if constexpr (F64)
-            FieldEval64<T, WPR>::eval(cz, set, tiles[wave], &red_own[g][0], q, lane, xin, yin, zs, phi, gx, gy, gz);
-          else
-            FieldEval32<T, WPR>::eval(cz, set, tiles[wave], tiles[g * WPR], q, lane, xin, yin, zs, phi, gx, gy,
+            FieldEval64<T, WPR>::eval(cz, set, tiles64[wave], &red_own[g][0], q, lane, xin, yin, zs, phi, gx, gy,
                                       gz);
+          else
+            FieldEval32<NW, WPR, T>::eval(cz, set, lds32, g, q, lane, xin, yin, zs, phi, gx, gy, gz);
         }
         const State& Yin = (stage == 0) ? Y : Ys;
         k = rhs(cz, Yin, phi, gx, gy, gz, a);
@@ -674,28 +694,29 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(OCC, OC
 // Field at arbitrary points: one wavefront = 63 points, no particle split.
 // Every group of 9 consecutive points is treated as a bundle: FP32 sums expand
 // about the first point of the group (rounded to FP32), as the trace kernel
-// does about a bundle's anchor, when the 63 points of the wavefront share z
-// (otherwise each point's sum is direct).
+// does about a bundle's anchor, when the points of the workgroup share z
+// (otherwise each point's sum is direct).  Wavefronts past the last point still
+// take part in the workgroup's tile rounds, on a copy of the last point.
 template <bool F64, int T>
 __global__ __launch_bounds__(256) void field_eval_kernel(DevCosmo c, const DevSet* set_p, int64_t n,
                                                          const double* pts, double* phi, double* grad) {
-  using Tile = typename TileSpace<F64, T>::Elem;
-  __shared__ Tile tiles[4][TileSpace<F64, T>::kElems];
+  __shared__ double4 tiles64[F64 ? 4 : 1][F64 ? T : 1];
+  __shared__ float4 lds32[Lds32Elems<F64, 4, 1, T>::v];
   // the wavefront index is uniform: keep it (and the tile loop counters) in SGPRs
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * kLanes;
-  if (w0 >= n) return;   // whole wavefront idle
   int64_t i = w0 + (lane < kLanes ? lane : kLanes - 1);
   const bool valid = lane < kLanes && i < n;
   if (i >= n) i = n - 1;
   const DevSet set = *set_p;
   double p, gx, gy, gz;
-  if constexpr (F64)
-    FieldEval64<T, 1>::eval(c, set, tiles[wave], nullptr, 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx, gy,
+  if constexpr (F64) {
+    if (w0 >= n) return;   // whole wavefront idle (no workgroup barriers in this path)
+    FieldEval64<T, 1>::eval(c, set, tiles64[wave], nullptr, 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx, gy,
                             gz);
-  else
-    FieldEval32<T, 1>::eval(c, set, tiles[wave], tiles[wave], 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx,
-                            gy, gz);
+  } else {
+    FieldEval32<4, 1, T>::eval(c, set, lds32, wave, 0, lane, pts[i], pts[n + i], pts[2 * n + i], p, gx, gy, gz);
+  }
   if (valid) {
     phi[i] = p;
     grad[i] = gx;
@@ -945,11 +966,11 @@ struct PlanShape {
   int nw, wpr, tile, occ;
 };
 
-// FP32: tiles of 288 particles (32 rounds of a bundle's nine lanes, 6.9 KB of
-// LDS) at four wavefronts per SIMD (128 registers) or three (168 registers),
-// and tiles of 576 at two (256 registers).
-constexpr PlanShape kPlans32[] = {{8, 1, 288, 4}, {8, 2, 288, 4}, {8, 4, 288, 4}, {8, 8, 288, 4},
-                                  {4, 1, 288, 3}, {4, 4, 288, 3}, {4, 1, 576, 2}, {4, 4, 576, 2}};
+// FP32: the workgroup's tiles and reduction area take at most 66 KB of LDS, so
+// two workgroups of 8 wavefronts (four per SIMD, 128 registers) or three of 4
+// (three per SIMD, 168 registers) fit a compute unit.
+constexpr PlanShape kPlans32[] = {{8, 1, 576, 4}, {8, 2, 576, 4}, {8, 4, 576, 4}, {8, 8, 288, 4},
+                                  {8, 1, 1152, 4}, {8, 2, 1152, 4}, {4, 1, 576, 3}, {4, 4, 288, 3}};
 constexpr PlanShape kPlans64[] = {{8, 1, 128, 4}, {8, 2, 128, 4}, {8, 4, 128, 4},
                                   {8, 8, 64, 4},  {4, 1, 128, 4}, {4, 4, 128, 4}};
 constexpr int kNumPlans32 = sizeof(kPlans32) / sizeof(kPlans32[0]);
