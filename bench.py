@@ -7,7 +7,8 @@ times with random shifts and rotations out to z_s = 0.5), 512 x 512 bundles
 softening 50 kpc/h; FP32 pair terms with Kahan sums, FP64 integration.
 
 One step = one pass of the hot path over one batch: a band of --band bundles
-of the row-major bundle grid advanced through a window of --window RK4 steps
+(7168 = 1024 wavefront groups of 7 bundles) of the row-major bundle grid
+advanced through a window of --window RK4 steps
 (rt_trace with a step window, one captured graph per window).  A band's first
 window starts with bundle construction (rt_build_bundles) and its last window
 ends with the magnification (rt_magnification) and the source-weighted muPDF
@@ -17,8 +18,8 @@ then through the bands.  Inputs (particles, bundle directions) are resident in
 HBM before the timed region.
 
 Reported beside the timed value (untimed):
-  * mixed vs FP64 on the GPU: a subsample of the first band traced through the
-    whole schedule in both precisions (same bundles, same launch shape): the
+  * mixed vs FP64 on the GPU: a subsample of the band through the centre of the
+    grid traced through the whole schedule in both precisions (same bundles): the
     mu error of the measurement contract (relative for |mu| <= 100, inverse
     beyond), exit positions, and the FP64 throughput of one full window of the
     band (the same launch shape as a timed step);
@@ -68,7 +69,7 @@ FLOP_PER_PAIR = 59.0
 FLOP_DIRECT = 20.0
 # FP64 direct sum per ray-particle interaction (same count as the direct term).
 FLOP_FP64 = 20.0
-# HBM bytes per launch of the FP32 trace kernel on the default workload (one 3584-bundle band,
+# HBM bytes per launch of the FP32 trace kernel on the default workload (one 7168-bundle band,
 # one 100-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain copy kernel, keyed by the sha256 prefix of the kernel sources they were taken with.
 MEASURED_TRAFFIC = {}
@@ -83,14 +84,14 @@ def parse():
                    choices=["box20", "box18", "nfw", "point", "batched", "nfw_pm", "box18_pm", "box20_pm",
                             "pm_study", "nfw_study", "soft_study"])
     p.add_argument("--band", type=int, default=0,
-                   help="bundles per step of the one-field workloads (0: 3584 for box20, 7168 for box18 and nfw)")
+                   help="bundles per step of the one-field workloads (0: 7168, i.e. 1024 groups of 7 bundles)")
     p.add_argument("--window", type=int, default=-1,
                    help="RK4 steps per bench step (0: the whole schedule; default 100 for the boxes, 0 otherwise)")
     p.add_argument("--side", type=int, default=0, help="batched: bundle grid side of every field (0: the "
                                                        "workload's own seeded 64/128/256)")
     p.add_argument("--precision", default="fp32k", choices=["fp32k", "fp64"])
     p.add_argument("--fp64-bundles", type=int, default=0,
-                   help="bundles of the first band traced through the whole schedule in both precisions for the "
+                   help="bundles of the central band traced through the whole schedule in both precisions for the "
                         "mu error (0: a default per workload)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
@@ -109,7 +110,7 @@ def parse():
                    help="only copy a buffer of this many MiB (HBM counter calibration) and exit")
     a = p.parse_args()
     if a.band == 0:
-        a.band = 3584 if a.workload in ("box20", "box20_pm") else 7168
+        a.band = 7168
     if a.window < 0:
         a.window = 100 if a.workload in ("box20", "box18") else 0
     return a
@@ -308,7 +309,7 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
     achieved = flop_launch / (k_ms * 1e-3) / 1e12
     sha = kernel_source_sha()
     m = MEASURED_TRAFFIC.get(sha)
-    traffic = (m["read"] + m["write"]) if (m and a.workload == "box20" and a.band == 3584 and win == 100
+    traffic = (m["read"] + m["write"]) if (m and a.workload == "box20" and a.band == 7168 and win == 100
                                            and prec == rt.RT_FP32_KAHAN and m.get("plan") == tuned) else None
     prec_name = "fp64" if prec == rt.RT_FP64 else "fp32 pair terms with Kahan sums, fp64 integration"
     result = {
@@ -340,8 +341,9 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
 
     # ---------------------------------------------------------------- mixed vs FP64 on the same bundles
     if not a.no_fp64 and prec != rt.RT_FP64:
-        b0 = bands[0]
-        nf = a.fp64_bundles or {"box20": 126, "box18": 504, "nfw": 7168, "point": 1024}.get(a.workload, 0)
+        # the band through the centre of the bundle grid (the halo core for the NFW workload)
+        b0 = bands[len(bands) // 2] if len(bands) > 1 else bands[0]
+        nf = a.fp64_bundles or {"box20": 504, "box18": 1024, "nfw": 7168, "point": 1024}.get(a.workload, 0)
         if a.workload == "batched":
             sub = b0
         else:
@@ -368,8 +370,8 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         m64, r64, ms64 = outs[rt.RT_FP64]
         st = mu_stats(m32, m64)
         st["gate_1e-4"] = mu_gate(m32, m64, 1e-4)
-        st["bundles"] = "%d bundles of the first band (every %s-th), whole schedule, both precisions on the GPU" % (
-            m64.size, "" if a.workload == "batched" else str(max(1, bands[0].fields[0].n_bundles // max(nf, 1))))
+        st["bundles"] = "%d bundles of the central band (every %s-th), whole schedule, both precisions on the GPU" % (
+            m64.size, "" if a.workload == "batched" else str(max(1, b0.fields[0].n_bundles // max(nf, 1))))
         result["mu_err_vs_fp64"] = st
         theta_sub = np.concatenate([f.theta for f in sub.fields], axis=1)
         result["exit_err_vs_fp64"] = exit_errors(r32, r64, theta_sub, w.bundle_radius, gs.chi_s)

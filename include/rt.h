@@ -129,10 +129,21 @@ rt_status rt_build_bundles(const rt_cosmology* cosmo, const rt_field* fields, in
  * Field at each stage: direct sum over the step's particle set plus the optional cuboid
  * background; Christoffel symbols differentiated exactly from eq. expandingmetric.
  * All fields are traced in one persistent launch with a work queue, captured once in a HIP
- * graph and replayed while the arguments stay the same; launches of one such configuration on
- * different streams are ordered one after the other (they share its FP32 copies and queue).
- * RT_FP32_KAHAN: a set whose masses are all equal (checked on the device at every call) takes
- * a loop that stages positions only and scales the sums by the common mass.
+ * graph and replayed while the arguments stay the same (the 24 most recent configurations are
+ * kept); launches of one such configuration on different streams are ordered one after the
+ * other (they share its FP32 copies and queue).  When `stream` is being captured, the launch
+ * becomes part of the caller's graph and the configuration's buffers are kept until
+ * rt_release_caches (which the caller must not call while such a graph may still run); the
+ * ordering between streams is then the caller's.
+ * RT_FP32_KAHAN: each (bundle, particle) pair is evaluated once for the bundle's nine rays, in
+ * FP32, at the bundle's expansion point (its anchor rounded to FP32): the pair's potential, field
+ * and their first and second derivatives with respect to the point (20 moments, Kahan-summed
+ * over tiles); each ray assembles its field in FP64 from the moments and its own offset (Sec.
+ * 3.1: the ring-minus-anchor differences keep FP32 relative precision).  Pairs closer than 1024
+ * times the bundle's largest ray offset are summed per ray directly in FP64; the truncation of
+ * the expansion stays below 6e-6 of each pair's ring difference.  Particle positions are held as
+ * two FP32 parts.  A set whose masses are all equal (checked on the device at every call) skips
+ * the per-pair mass product.
  * rays: device [8][9 n_bundles], updated in place.  ray_flags: device [9 n_bundles] or NULL;
  * bits are OR-ed in: 1 non-finite state, 2 kz <= 0 (ray turned back), 4 |phi|/a > 1e-2 (outside
  * the weak-field regime of Sec. 3.2).  A ray with flag 1 or 2 keeps its last good state.

@@ -215,6 +215,7 @@ struct TraceEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;   // recorded after every launch of the graph
+  bool pinned = false;         // launched into a caller's graph: kept until rt_release_caches
   ~TraceEntry() {
     // an evicted entry may still be running: its buffers are freed only after it ends
     if (done) {
@@ -239,7 +240,9 @@ struct State {
   rt_trace_info last{};
 } g;
 
-constexpr size_t kMaxEntries = 8;
+// Configurations kept (a benchmark walks 20 step windows of one band, and each
+// window is a configuration of its own).
+constexpr size_t kMaxEntries = 24;
 
 template <class T>
 void put(std::vector<uint8_t>& k, const T& v) {
@@ -678,7 +681,15 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
                           rays, ray_flags)) != RT_OK)
       return st;
     if ((st = capture_entry(fresh.get())) != RT_OK) return st;
-    if (g.cache.size() >= kMaxEntries) g.cache.erase(g.cache.begin());
+    // evict the least recently used entry that no caller's graph refers to
+    if (g.cache.size() >= kMaxEntries) {
+      for (size_t i = 0; i < g.cache.size(); ++i) {
+        if (!g.cache[i]->pinned) {
+          g.cache.erase(g.cache.begin() + i);
+          break;
+        }
+      }
+    }
     g.cache.push_back(std::move(fresh));
     e = g.cache.back().get();
   }
@@ -698,8 +709,17 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
     if (!g.ev1) RT_HIP(hipEventCreate(&g.ev1));
     RT_HIP(hipEventRecord(g.ev0, stream));
   }
-  RT_HIP(hipGraphLaunch(e->exec, stream));
-  if (ordered) RT_HIP(hipEventRecord(e->done, stream));
+  if (ordered) {
+    RT_HIP(hipGraphLaunch(e->exec, stream));
+    RT_HIP(hipEventRecord(e->done, stream));
+  } else {
+    // The caller is capturing its own graph: enqueue the kernels themselves so that
+    // they are recorded there (a graph launched into a capture is not).  They keep
+    // referring to this entry's buffers on every replay, after this call returns:
+    // the entry is never evicted.
+    if ((st = enqueue_entry(e, stream)) != RT_OK) return st;
+    e->pinned = true;
+  }
   if (g.timing) RT_HIP(hipEventRecord(g.ev1, stream));
   g.timed_last = g.timing;
   g.last.kernel_ms = 0.0;

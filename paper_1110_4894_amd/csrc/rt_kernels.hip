@@ -141,6 +141,7 @@ __device__ __forceinline__ int lane_segment(int lane) { return lane < kLanes ? l
 // (boxes: 71 kpc against a few parsecs) skip the nearness test altogether.
 // ===========================================================================
 constexpr int kMom = 20;
+constexpr int kKahanRounds = 64;         // rounds of plain FP32 sums between compensated adds
 constexpr float kNearRatio2 = 1048576.f;   // (1024)^2
 constexpr float kNearFloor2 = 1e-8f;     // (1e-4 Mpc)^2
 // LDS bytes per wavefront of the FP32 path: its tile, and at least what its
@@ -268,8 +269,6 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
 template <bool EQUAL, bool DETECT, bool EXCLUDE>
 __device__ __forceinline__ bool tile_moments(const float4* tile, const float2* tlo, int rounds, int l, float ex,
                                              float ey, float e2, float thr, float (&a)[kMom]) {
-#pragma unroll
-  for (int k = 0; k < kMom; ++k) a[k] = 0.f;
   bool any_near = false;
 #pragma unroll 4
   for (int i = 0; i < rounds; ++i)
@@ -294,6 +293,12 @@ __device__ void moment_tiles(const DevSet& s, float4* tile, int q, int g, int la
   float2* tlo = reinterpret_cast<float2*>(tile + TP);
   // the stage's z in two FP32 parts
   const float zr_hi = (float)zrel, zr_lo = (float)(zrel - (double)zr_hi);
+  // unguarded sums: plain FP32 over kKahanRounds rounds (whatever the tile size), then Kahan
+  constexpr int kTilesPerKahan = (kKahanRounds * 9 + TP - 1) / TP;
+  float acc[kMom];
+#pragma unroll
+  for (int k = 0; k < kMom; ++k) acc[k] = 0.f;
+  int since = 0;
   for (int64_t it = 0; it < n_rounds; ++it) {
     const int64_t ch = q + it * WPR;
     const int64_t base = ch * TP;
@@ -322,18 +327,34 @@ __device__ void moment_tiles(const DevSet& s, float4* tile, int q, int g, int la
       const int64_t left = n - base;
       // a set's last tile runs only over its particles
       const int rounds = left >= TP ? TP / 9 : (int)((left + 8) / 9);
-      float a[kMom];
-      const bool near = tile_moments<EQUAL, GUARD, false>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
       if constexpr (GUARD) {
+        // per tile: a tile holding a near pair is summed again without it
+        float a[kMom];
+#pragma unroll
+        for (int k = 0; k < kMom; ++k) a[k] = 0.f;
+        const bool near = tile_moments<EQUAL, true, false>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
         if (__any(near)) {
+#pragma unroll
+          for (int k = 0; k < kMom; ++k) a[k] = 0.f;
           tile_moments<EQUAL, false, true>(tile, tlo, rounds, l, ex, ey, e2, thr, a);
           const int cnt = left >= TP ? TP : (int)left;
 #pragma unroll 1
           for (int j = 0; j < cnt; ++j) near_direct<EQUAL>(tile[j], tlo[j], ex, ey, e2, thr, dx, dy, dz, dir);
         }
-      }
 #pragma unroll
-      for (int k = 0; k < kMom; ++k) kahan_add(ks[k], kc[k], a[k]);
+        for (int k = 0; k < kMom; ++k) kahan_add(ks[k], kc[k], a[k]);
+      } else {
+        // plain sums over kKahanRounds rounds of the nine lanes, then one compensated add
+        tile_moments<EQUAL, false, false>(tile, tlo, rounds, l, ex, ey, e2, thr, acc);
+        if (++since >= kTilesPerKahan || ch + WPR >= n_tiles) {
+#pragma unroll
+          for (int k = 0; k < kMom; ++k) {
+            kahan_add(ks[k], kc[k], acc[k]);
+            acc[k] = 0.f;
+          }
+          since = 0;
+        }
+      }
     }
     __syncthreads();   // before the tile is staged again
   }

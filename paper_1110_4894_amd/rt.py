@@ -61,7 +61,8 @@ class rt_pm_grid(C.Structure):
 
 
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
-           "rt_magnification", "rt_mu_histogram", "rt_shear_histogram", "rt_field_eval", "rt_plan_count", "rt_plan_describe",
+           "rt_magnification", "rt_mu_histogram", "rt_shear_histogram", "rt_field_eval",
+           "rt_plan_count", "rt_plan_describe",
            "rt_force_plan", "rt_set_grid_limit", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
            "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda", "rt_sync"]
 
