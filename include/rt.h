@@ -168,6 +168,15 @@ rt_status rt_magnification(const rt_cosmology* cosmo, double z_source, int64_t n
 rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
                           double* pdf, double* moments, hipStream_t stream);
 
+/* rt_mu_histogram for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and results, with the
+ * per-call scratch (the bin weights and five sums) in a static per-device array of the library
+ * instead of a stream-ordered allocation.  It calls no allocating routine.  n_bins <= 65536
+ * (RT_ERR_INVALID_ARG beyond).  Every call on one GPU shares that GPU's array (512 KB, held
+ * until the process ends): calls that overlap on one GPU (on different streams) race. */
+rt_status rt_mu_histogram_noalloc(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
+                                  double* pdf, double* moments, hipStream_t stream);
+
 /* Source-weighted shear PDF (the shear distribution of Sec. 5.4, weighted like eq. weighthisto):
  * |gamma| = hypot(gamma1, gamma2) from rt_magnification's Jacobian, weight 1/mu for mu > 0,
  * n_bins bins uniform in |gamma| over [lo, hi); pdf_i = sum_{b in i} w_b / (sum_b w_b dgamma).

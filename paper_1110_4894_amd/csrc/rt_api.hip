@@ -760,6 +760,22 @@ rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double lo
   return RT_OK;
 }
 
+rt_status rt_mu_histogram_noalloc(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
+                                  double* pdf, double* moments, hipStream_t stream) {
+  if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");
+  if (n > 0 && !mu) return fail(RT_ERR_INVALID_ARG, "mu is NULL");
+  if (!pdf || !moments) return fail(RT_ERR_INVALID_ARG, "pdf or moments is NULL");
+  if (!std::isfinite(log_lo) || !std::isfinite(log_hi)) return fail(RT_ERR_NONFINITE, "histogram range");
+  if (!(log_hi > log_lo)) return fail(RT_ERR_INVALID_ARG, "log_hi must exceed log_lo");
+  double* work = nullptr;
+  int32_t max_bins = 0;
+  RT_HIP(noalloc_scratch(&work, &max_bins));
+  if (n_bins < 1 || n_bins > max_bins)
+    return fail(RT_ERR_INVALID_ARG, "n_bins = %d must be in [1, %d] (the static scratch)", n_bins, max_bins);
+  RT_HIP(launch_histogram(n, mu, nullptr, 0, n_bins, log_lo, log_hi, pdf, moments, work, stream));
+  return RT_OK;
+}
+
 rt_status rt_shear_histogram(int64_t n, const double* mu, const double* jac, int32_t n_bins, double lo, double hi,
                              double* pdf, double* moments, hipStream_t stream) {
   if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");

@@ -77,6 +77,9 @@ hipError_t launch_field_eval(DevCosmo c, const DevSet* set, bool fp64, int64_t n
                              double* grad, hipStream_t s);
 hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const double* rays, double* mu,
                                 double* jac, hipStream_t s);
+// The static scratch of rt_mu_histogram_noalloc on the current device (its address is
+// looked up once per device) and the largest bin count it holds.
+hipError_t noalloc_scratch(double** out, int32_t* max_bins);
 hipError_t launch_histogram(int64_t n, const double* mu, const double* jac, int mode, int32_t n_bins, double lo,
                             double hi, double* pdf, double* moments, double* work, hipStream_t s);
 

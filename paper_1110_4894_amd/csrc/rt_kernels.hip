@@ -28,6 +28,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "rt_geodesic.h"
@@ -1096,6 +1098,35 @@ hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const d
   hipLaunchKernelGGL(magnification_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, chi_s, nb, radius,
                      rays, mu, jac);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the histogram entry point that allocates nothing
+// (rt_mu_histogram_noalloc): the bin weights and the five sums of one call,
+// for at most kNoAllocBins bins.  Each GPU holds its own copy of the array;
+// host code uses the per-device address from hipGetSymbolAddress, never the
+// array's name.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocBins = 65536;
+static __device__ __align__(256) double scratch[kNoAllocBins + 8];
+
+hipError_t noalloc_scratch(double** out, int32_t* max_bins) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;   // device -> address of its copy of scratch
+  int dev;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, ptr).first;
+  }
+  *out = static_cast<double*>(it->second);
+  *max_bins = kNoAllocBins;
+  return hipSuccess;
 }
 
 hipError_t launch_histogram(int64_t n, const double* mu, const double* jac, int mode, int32_t n_bins, double lo,

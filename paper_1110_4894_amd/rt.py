@@ -61,7 +61,7 @@ class rt_pm_grid(C.Structure):
 
 
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
-           "rt_magnification", "rt_mu_histogram", "rt_shear_histogram", "rt_field_eval",
+           "rt_magnification", "rt_mu_histogram", "rt_mu_histogram_noalloc", "rt_shear_histogram", "rt_field_eval",
            "rt_plan_count", "rt_plan_describe",
            "rt_force_plan", "rt_set_grid_limit", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
            "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda", "rt_sync"]
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
         "rt_trace": (st, [p, d, p, i32, st, i32, i32, i64, p, p, p]),
         "rt_magnification": (st, [p, d, i64, d, p, p, p, p]),
         "rt_mu_histogram": (st, [i64, p, i32, d, d, p, p, p]),
+        "rt_mu_histogram_noalloc": (st, [i64, p, i32, d, d, p, p, p]),
         "rt_shear_histogram": (st, [i64, p, p, i32, d, d, p, p, p]),
         "rt_field_eval": (st, [p, p, st, i64, p, p, p, p]),
         "rt_plan_count": (i32, [st]),
@@ -226,6 +227,11 @@ def rt_magnification(cosmo, z_source: float, n_bundles: int, radius: float, rays
 def rt_mu_histogram(n: int, mu, n_bins: int, log_lo: float, log_hi: float, pdf, moments, stream=None):
     _check(load().rt_mu_histogram(int(n), _dptr(mu), int(n_bins), float(log_lo), float(log_hi), _dptr(pdf),
                                   _dptr(moments), _stream(stream)))
+
+
+def rt_mu_histogram_noalloc(n: int, mu, n_bins: int, log_lo: float, log_hi: float, pdf, moments, stream=None):
+    _check(load().rt_mu_histogram_noalloc(int(n), _dptr(mu), int(n_bins), float(log_lo), float(log_hi), _dptr(pdf),
+                                          _dptr(moments), _stream(stream)))
 
 
 def rt_shear_histogram(n: int, mu, jac, n_bins: int, lo: float, hi: float, pdf, moments, stream=None):
