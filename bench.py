@@ -93,6 +93,8 @@ def parse():
     p.add_argument("--fp64-bundles", type=int, default=0,
                    help="bundles of the central band traced through the whole schedule in both precisions for the "
                         "mu error (0: a default per workload)")
+    p.add_argument("--tune-steps", type=int, default=0,
+                   help="RK4 steps each plan is timed on by the autotuner (0: 6, 1 for batched)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-autotune", action="store_true")
@@ -252,7 +254,8 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         tuned = a.plan
     elif not a.no_autotune:
         g.build_bundles()
-        tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, prec, n_rk // 2, min(6, win), g.n_bundles, g.rays)
+        ts = a.tune_steps or (1 if a.workload == "batched" else 6)
+        tuned = rt.rt_autotune(g.cosmo, w.z_source, g.table, prec, n_rk // 2, min(ts, win), g.n_bundles, g.rays)
         say("autotune: plan %d %s" % (tuned, rt.rt_plan_describe(prec, tuned)))
 
     pdf = mom = None
@@ -345,7 +348,8 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         b0 = bands[len(bands) // 2] if len(bands) > 1 else bands[0]
         nf = a.fp64_bundles or {"box20": 504, "box18": 1024, "nfw": 7168, "point": 1024}.get(a.workload, 0)
         if a.workload == "batched":
-            sub = b0
+            # the same 64 fields with 16 x 16 bundles each (the full grids would take an hour in FP64)
+            sub = workloads.batched(side_override=16)
         else:
             f = b0.fields[0]
             stride = max(1, f.n_bundles // nf)
@@ -370,8 +374,12 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         m64, r64, ms64 = outs[rt.RT_FP64]
         st = mu_stats(m32, m64)
         st["gate_1e-4"] = mu_gate(m32, m64, 1e-4)
-        st["bundles"] = "%d bundles of the central band (every %s-th), whole schedule, both precisions on the GPU" % (
-            m64.size, "" if a.workload == "batched" else str(max(1, b0.fields[0].n_bundles // max(nf, 1))))
+        if a.workload == "batched":
+            st["bundles"] = ("%d bundles: the same 64 fields with 16 x 16 bundles each, whole schedules, both "
+                             "precisions on the GPU" % m64.size)
+        else:
+            st["bundles"] = ("%d bundles of the central band (every %d-th), whole schedule, both precisions on the "
+                             "GPU" % (m64.size, max(1, b0.fields[0].n_bundles // max(nf, 1))))
         result["mu_err_vs_fp64"] = st
         theta_sub = np.concatenate([f.theta for f in sub.fields], axis=1)
         result["exit_err_vs_fp64"] = exit_errors(r32, r64, theta_sub, w.bundle_radius, gs.chi_s)

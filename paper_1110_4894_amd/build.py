@@ -30,6 +30,40 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def llvm_tool(name: str) -> str:
+    for d in ("/opt/rocm/llvm/bin", "/opt/rocm/lib/llvm/bin"):
+        p = os.path.join(d, name)
+        if os.path.exists(p):
+            return p
+    return name
+
+
+def check_no_calls(obj: str) -> None:
+    """Every device function of the library is inlined into its kernel.  A large
+    called function reaches its far blocks through long branches, and the
+    compiler builds their targets in the register pair that holds the
+    function's return address, so such a function may never return.  Fail the
+    build if a gfx950 kernel of this object calls anything."""
+    import tempfile
+    sections = subprocess.run([llvm_tool("llvm-readobj"), "--sections", obj], check=True, capture_output=True,
+                              text=True).stdout
+    if ".hip_fatbin" not in sections:
+        return   # host code only
+    with tempfile.TemporaryDirectory() as tmp:
+        fat = os.path.join(tmp, "fatbin")
+        co = os.path.join(tmp, "co")
+        subprocess.run([llvm_tool("llvm-objcopy"), "--dump-section=.hip_fatbin=" + fat, obj], check=True)
+        subprocess.run([llvm_tool("clang-offload-bundler"), "--unbundle", "--type=o",
+                        "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat, "--output=" + co],
+                       check=True)
+        dis = subprocess.run([llvm_tool("llvm-objdump"), "-d", "--mcpu=gfx950", co], check=True,
+                             capture_output=True, text=True).stdout
+    bad = [l.strip() for l in dis.splitlines() if "s_swappc_b64" in l or "s_getpc_b64 s[30:31]" in l]
+    if bad:
+        raise RuntimeError("%s: gfx950 code calls a device function (%d instructions, e.g. %s); mark it "
+                           "__forceinline__" % (os.path.basename(obj), len(bad), bad[0]))
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source to an object (in parallel), then link librt.so."""
     from concurrent.futures import ThreadPoolExecutor
@@ -44,6 +78,8 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         list(ex.map(compile_one, range(len(SOURCES))))
+    for o in objs:
+        check_no_calls(o)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:

@@ -282,7 +282,7 @@ __device__ __forceinline__ bool tile_moments(const float4* tile, const float2* t
 // number of rounds: in round it, the NG wavefronts of index q stage tile
 // q + it WPR together and each sums it for its own bundles.
 template <int TP, int WPR, int NG, bool EQUAL, bool GUARD>
-__device__ void moment_tiles(const DevSet& s, float4* tile, int q, int g, int lane, float ex, float ey, float thr,
+__device__ __forceinline__ void moment_tiles(const DevSet& s, float4* tile, int q, int g, int lane, float ex, float ey, float thr,
                              float dx, float dy, float dz, double zrel, float (&ks)[kMom], float (&kc)[kMom],
                              double (&dir)[4]) {
   const int64_t n = s.n;
@@ -362,6 +362,21 @@ __device__ void moment_tiles(const DevSet& s, float4* tile, int q, int g, int la
   }
 }
 
+// A set of at most kSmallSet particles (point-mass lenses) is summed directly at
+// every ray in FP64, with the particles read by every lane from the caller's
+// array: a few FP64 pair terms per stage cost less than the moments'
+// reduction, and are exact.  (Every wavefront of a workgroup takes this path for
+// the same set, so it needs no barrier.)
+constexpr int64_t kSmallSet = 63;
+
+__device__ __forceinline__ void small_set_fp64(const DevCosmo& c, const DevSet& s, double x, double y, double z,
+                                               double& phi, double& gx, double& gy, double& gz);
+
+// (Every device function on the trace path is inlined into its kernel: a large
+// called function reaches its far blocks through long branches, and the
+// compiler builds their targets in the register pair that holds the function's
+// return address.)
+//
 // Field of one set at the lane's ray (FP32 pair terms).  The WPR wavefronts of
 // a group hold the same rays and split the tiles; all wavefronts of the
 // workgroup share the staged tiles.  The group's partial moments meet in LDS
@@ -372,8 +387,13 @@ struct FieldEval32 {
   static constexpr int NG = NW / WPR;
   using L = Lds32<NW, WPR, TP>;
 
-  __device__ static void eval(const DevCosmo& c, const DevSet& s, float4* lds, int g, int q, int lane, double x,
-                              double y, double z, double& phi, double& gx, double& gy, double& gz) {
+  __device__ __forceinline__ static void eval(const DevCosmo& c, const DevSet& s, float4* lds, int g, int q, int lane,
+                                              double x, double y, double z, double& phi, double& gx, double& gy,
+                                              double& gz) {
+    if (s.n <= kSmallSet) {
+      small_set_fp64(c, s, x, y, z, phi, gx, gy, gz);
+      return;
+    }
     // positions in the set's frame (FP64); each bundle's expansion point is its
     // anchor rounded to FP32; each ray's offset from it in FP32
     const double X = x - s.org[0], Yv = y - s.org[1], Zl = z - s.org[2];
@@ -520,6 +540,28 @@ __device__ __forceinline__ void pair_fp64_unit(const double4 c, double x, double
   a3 = fma(r3, ez, a3);
 }
 
+__device__ __forceinline__ void small_set_fp64(const DevCosmo& c, const DevSet& s, double x, double y, double z,
+                                               double& phi, double& gx, double& gy, double& gz) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int64_t n = s.n;
+  const double* __restrict__ px = s.p64;
+#pragma unroll 1
+  for (int64_t j = 0; j < n; ++j)
+    pair_fp64(make_double4(px[j], px[n + j], px[2 * n + j], px[3 * n + j]), x, y, z, s.eps2, a0, a1, a2, a3);
+  phi = -c.G * a0;
+  gx = -c.G * a1;
+  gy = -c.G * a2;
+  gz = -c.G * a3;
+  if (s.background) {
+    double U, ux, uy, uz;
+    cuboid_field(s.lo, s.hi, x, y, z, U, ux, uy, uz);
+    phi += c.G_rho * U;
+    gx += c.G_rho * ux;
+    gy += c.G_rho * uy;
+    gz += c.G_rho * uz;
+  }
+}
+
 // UNIT: every mass equals s.mass, which multiplies the finished sums.
 template <int T, int WPR, bool UNIT>
 __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, int lane, double x, double y,
@@ -568,8 +610,9 @@ __device__ __forceinline__ void sum_fp64(const DevSet& s, double4* tile, int q, 
 // from the set's device flag.
 template <int T, int WPR>
 struct FieldEval64 {
-  __device__ static void eval(const DevCosmo& c, const DevSet& s, double4* tile, double* red, int q, int lane,
-                              double x, double y, double z, double& phi, double& gx, double& gy, double& gz) {
+  __device__ __forceinline__ static void eval(const DevCosmo& c, const DevSet& s, double4* tile, double* red, int q,
+                                              int lane, double x, double y, double z, double& phi, double& gx,
+                                              double& gy, double& gz) {
     double S0, Sx, Sy, Sz;
     if (s.equal_mass && *s.equal_mass)
       sum_fp64<T, WPR, true>(s, tile, q, lane, x, y, z, S0, Sx, Sy, Sz);
