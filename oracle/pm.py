@@ -279,20 +279,49 @@ def trace_pm_steps(c, nodes, rays, grids, step_grid, n_int, step_begin=0, step_e
 
 
 def trace_pm_lambda(c, chi_s, rays, fields, fields_y2z, origin, h, n_int, f_rk, max_steps):
+    """trace_pm_lambda_slabs with one isolated grid as the field everywhere."""
+    grid = (fields, fields_y2z, origin, h, False)
+    return trace_pm_lambda_slabs(c, chi_s, rays, [grid], np.array([-np.inf, np.inf]), np.zeros(1, np.int64), h,
+                                 n_int, f_rk, max_steps)
+
+
+def slab_field(grids, bounds, slab_grid, n_int, p) -> np.ndarray:
+    """(phi, grad) at p from the grid of the slab holding p[2]: bounds[k] <= p[2] < bounds[k + 1]
+    takes grid slab_grid[k] (none for -1); zero outside [bounds[0], bounds[-1])."""
+    z = p[2]
+    if not (bounds[0] <= z < bounds[-1]):
+        return np.zeros(4)
+    k = int(np.searchsorted(bounds, z, side="right")) - 1
+    gi = int(slab_grid[k])
+    if gi < 0:
+        return np.zeros(4)
+    F, F2, org, hh, periodic = grids[gi]
+    ev = appb_eval_periodic if periodic else appb_eval
+    return ev(F, F2, org, hh, n_int, p)
+
+
+def trace_pm_lambda_slabs(c, chi_s, rays, grids, bounds, slab_grid, h, n_int, f_rk, max_steps):
     """The paper's own integrator (Sec. 3.4, eq. RKstepsize): classical RK4 in the affine
-    parameter with the fixed step  d_lambda = f_RK h / kz_0  (h: the grid spacing, L_box /
-    n_FFT; kz_0: the ray's dz/dlambda at the observer), repeated until z reaches chi_s; the
-    step that overshoots is replaced by the linear interpolation between the previous and
+    parameter with the fixed step  d_lambda = f_RK h / kz_0  (h: the Fourier-grid spacing,
+    L_box / n_FFT; kz_0: the ray's dz/dlambda at the observer), repeated until z reaches chi_s;
+    the step that overshoots is replaced by the linear interpolation between the previous and
     the current state at z = chi_s.  State (t, x, y, z, kt, kx, ky, kz), d/dlambda = (kt, kx,
     ky, kz, -A^t, -A^x, -A^y, -A^z) with the Christoffel contraction A of the z-form.
+
+    The field at a point is looked up by its own x^3 (Sec. 5.2: the space between observer and
+    source is filled by a stack of cubes along the line of sight, each with its own grid): the
+    slabs bounds[k] <= x^3 < bounds[k + 1] take grid slab_grid[k] (none for -1), by App. B; a
+    point outside [bounds[0], bounds[-1]) sees no field.  grids: list of (fields [4,n,n,n],
+    x^3 splines [4,n,n,n], origin, h, periodic).
     Flags: 1 non-finite, 2 kz <= 0 (both freeze the ray), 4 |phi|/a > 1e-2, 8 chi_s not
     reached within max_steps.  rays [8, R] are updated in place; returns (rays, flags, steps)."""
     from . import accel, scale_factor
+    bounds = np.asarray(bounds, dtype=np.float64)
     flags = np.zeros(rays.shape[1], dtype=np.uint8)
     steps = np.zeros(rays.shape[1], dtype=np.int64)
 
     def f(Y):
-        q = appb_eval(fields, fields_y2z, origin, h, n_int, Y[1:4])
+        q = slab_field(grids, bounds, slab_grid, n_int, Y[1:4])
         A = accel(c, Y[0], Y[4:8], q[0], q[1:])
         return np.concatenate([Y[4:8], -A]), q[0]
 

@@ -219,6 +219,73 @@ def test_lambda_integrator_converges_to_the_z_integrator():
     assert errs[0] > 20 * errs[1]
 
 
+def test_slab_lookup_takes_the_grid_of_the_slab_holding_the_point():
+    """Sec. 5.2 stack of cubes along the line of sight: grid k holds the constant field k + 1
+    (App. B reproduces constants exactly), so the looked-up value names the grid used."""
+    n, h = 4, 1.0
+    grids = []
+    for k in range(3):
+        F = np.full((4, n, n, n), k + 1.0)
+        grids.append((F, np.zeros_like(F), np.array([-2.0, -2.0, 4.0 * k]), h, True))
+    bounds = np.array([0.0, 4.0, 8.0, 12.0, 16.0])
+    slab_grid = np.array([0, 2, -1, 1])
+    want = {-1e-12: 0.0, 0.0: 1.0, 3.999: 1.0, 4.0: 3.0, 7.5: 3.0, 8.0: 0.0, 11.9: 0.0, 12.0: 2.0, 15.999: 2.0,
+            16.0: 0.0, 1e3: 0.0}
+    for z, v in want.items():
+        got = pm.slab_field(grids, bounds, slab_grid, 2, np.array([0.3, -0.7, z]))
+        assert np.all(got == v), (z, got)
+
+
+def _smooth_periodic_grid(n, h, z0, amp, x0, y0):
+    """A periodic grid holding phi = amp sin^2(pi (z - z0) / L) cos(k (x - x0)) cos(k (y - y0))
+    (L = n h, k = 2 pi / L) and its gradient: zero with zero slope on the faces z = z0 + j L."""
+    L = n * h
+    origin = np.array([-0.5 * L, -0.5 * L, z0])
+    u = np.arange(n) * h
+    X, Y, Z = np.meshgrid(origin[0] + u, origin[1] + u, origin[2] + u, indexing="ij")
+    k = 2 * np.pi / L
+    sz, cx, cy = np.sin(np.pi * (Z - z0) / L) ** 2, np.cos(k * (X - x0)), np.cos(k * (Y - y0))
+    F = np.array([amp * sz * cx * cy, -amp * k * sz * np.sin(k * (X - x0)) * cy,
+                  -amp * k * sz * cx * np.sin(k * (Y - y0)),
+                  amp * np.pi / L * np.sin(2 * np.pi * (Z - z0) / L) * cx * cy])
+    return (F, pm.spline_y2_periodic(F, h), origin, h, True)
+
+
+def test_lambda_integrator_through_a_stack_of_slabs_converges_to_the_z_integrator():
+    """Two adjacent periodic cubes of different fields, each looked up only inside its own
+    slab (Sec. 5.2), traced by the lambda-stepping RK4 (Sec. 3.4, eq. RKstepsize) and by the
+    z-stepping RK4 with nodes on the slab faces (where its step-midpoint choice of grid is the
+    per-point choice exactly).  The fields vanish with zero slope on the faces, so the lambda
+    steps that straddle a face cost little and the two converge as f_RK shrinks; a lookup that
+    misplaced the faces by half a grid spacing, or took the wrong grid, would miss by 1e-3
+    and 1e-1 of the deflection."""
+    c = orc.cosmo()
+    chi_s = orc.comoving_distance(c, 0.02)
+    n, h = 8, 0.5
+    grids = [_smooth_periodic_grid(n, h, 20.0, 3e-6, 0.3, -0.2), _smooth_periodic_grid(n, h, 24.0, -2e-6, -0.5, 0.9)]
+    bounds = np.array([20.0, 24.0, 28.0])
+    theta = np.array([[0.02], [0.015]])
+    radius = 0.05 * math.pi / 180 / 3600
+    nodes = np.concatenate([np.linspace(0, 20, 21)[:-1], np.linspace(20, 28, 161)[:-1], np.linspace(28, chi_s, 41)])
+    mid = 0.5 * (nodes[1:] + nodes[:-1])
+    step_grid = np.where((mid >= 20) & (mid < 24), 0, np.where((mid >= 24) & (mid < 28), 1, -1))
+    ref, fl = pm.trace_pm_steps(c, nodes, _empty_field_rays(c, theta, radius, nodes), grids, step_grid, 2)
+    assert not fl.any()
+    mu_ref, _ = orc.magnification(chi_s, ref, radius)
+    defl = np.hypot(ref[1] - np.repeat(theta[0], 9) * chi_s, ref[2] - np.repeat(theta[1], 9) * chi_s)
+    assert defl.min() > 5e-4                           # the rays are deflected
+    errs = []
+    for f_rk in (2.0, 0.25):
+        out, flags, steps = pm.trace_pm_lambda_slabs(c, chi_s, _empty_field_rays(c, theta, radius, nodes), grids,
+                                                     bounds, np.array([0, 1]), h, 2, f_rk, 10 ** 6)
+        assert not flags.any()
+        assert np.all(np.abs(out[3] / chi_s - 1) < 1e-13)
+        mu, _ = orc.magnification(chi_s, out, radius)
+        errs.append(max(np.max(np.hypot(out[1] - ref[1], out[2] - ref[2]) / defl), abs(mu[0] / mu_ref[0] - 1)))
+    assert errs[1] < 2e-5
+    assert errs[0] > 10 * errs[1]
+
+
 def test_periodic_deposit_wraps_and_conserves_mass():
     n, h, origin = 8, 0.5, np.zeros(3)
     rng = np.random.default_rng(8)
