@@ -71,7 +71,7 @@ FLOP_DIRECT = 20.0
 FLOP_FP64 = 20.0
 # HBM bytes per launch of the FP32 trace kernel on the default workload (one 7168-bundle band,
 # one 100-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
-# plain copy kernel, keyed by the sha256 prefix of the kernel sources they were taken with.
+# plain copy kernel, keyed by trace_kernel_code_sha of the kernel they were taken on.
 MEASURED_TRAFFIC = {}
 
 
@@ -118,11 +118,38 @@ def parse():
     return a
 
 
-def kernel_source_sha() -> str:
-    """sha256 prefix of the trace kernel's code (its kernel file and the shared headers)."""
-    h = hashlib.sha256()
-    for f in ("rt_kernels.hip", "rt_geodesic.h", "rt_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_1110_4894_amd", "csrc", f), "rb").read())
+def trace_kernel_code_sha(plan_desc, fp64=False):
+    """sha256 prefix of the gfx950 instructions of one trace kernel plan in the built
+    library (this build's own code object, disassembled), or None if the tools are
+    missing: the key under which measured HBM traffic is recorded, so that a figure is
+    used only for the very kernel it was taken on."""
+    import subprocess
+    import tempfile
+    from paper_1110_4894_amd import build as libbuild
+    name = "trace_kernel<%s, %d, %d, %d, %d>" % ("true" if fp64 else "false", plan_desc["waves_per_block"],
+                                                 plan_desc["waves_per_group"], plan_desc["tile"],
+                                                 plan_desc["waves_per_simd"])
+    lib = os.path.join(ROOT, "paper_1110_4894_amd", "librt.so")
+    try:
+        with tempfile.TemporaryDirectory() as tmp:
+            fat, co = os.path.join(tmp, "fat"), os.path.join(tmp, "co")
+            subprocess.run([libbuild.llvm_tool("llvm-objcopy"), "--dump-section=.hip_fatbin=" + fat, lib], check=True,
+                           capture_output=True)
+            subprocess.run([libbuild.llvm_tool("clang-offload-bundler"), "--unbundle", "--type=o",
+                            "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat, "--output=" + co],
+                           check=True, capture_output=True)
+            dis = subprocess.run([libbuild.llvm_tool("llvm-objdump"), "-d", "-C", "--no-show-raw-insn",
+                                  "--no-leading-addr", "--mcpu=gfx950", co], check=True, capture_output=True,
+                                 text=True).stdout
+    except (OSError, subprocess.CalledProcessError):
+        return None
+    h, inside = hashlib.sha256(), False
+    for line in dis.splitlines():
+        if line.endswith(">:") or line.endswith(":") and not line.startswith(" "):
+            inside = name in line and "TraceParams" in line
+            continue
+        if inside and line.strip():
+            h.update(line.split("//")[0].strip().encode())
     return h.hexdigest()[:16]
 
 
@@ -310,10 +337,11 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
     else:
         flop_launch, peak = flop_pair * pairs_launch, PEAK_FP32
     achieved = flop_launch / (k_ms * 1e-3) / 1e12
-    sha = kernel_source_sha()
-    m = MEASURED_TRAFFIC.get(sha)
+    plan_used = rt.rt_last_trace_info()["plan_id"]
+    code_sha = trace_kernel_code_sha(rt.rt_plan_describe(prec, plan_used), prec == rt.RT_FP64)
+    m = MEASURED_TRAFFIC.get(code_sha)
     traffic = (m["read"] + m["write"]) if (m and a.workload == "box20" and a.band == 7168 and win == 100
-                                           and prec == rt.RT_FP32_KAHAN and m.get("plan") == tuned) else None
+                                           and prec == rt.RT_FP32_KAHAN) else None
     prec_name = "fp64" if prec == rt.RT_FP64 else "fp32 pair terms with Kahan sums, fp64 integration"
     result = {
         "metric": METRIC, "value": value, "unit": "ray-particle interactions/s", "n_gpus": 1,
@@ -328,6 +356,7 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         "interactions_per_bundle": inter_per_bundle,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch (read + write)",
+                     "kernel_code_sha": code_sha,
                      "kernel": "trace_kernel (%s)" % ("fp64" if prec == rt.RT_FP64 else "fp32"),
                      "kernel_ms": k_ms, "launch_interactions": inter_launch,
                      "flop_per_unit": FLOP_FP64 if prec == rt.RT_FP64 else flop_pair,
@@ -713,7 +742,7 @@ def bench_soft_study(a, torch, rt, workloads, GpuRun, dev):
     softenings: the paper's 5 and 16 h^-1 kpc and the workload's 50 h^-1 kpc."""
     rows = []
     for soft in (5.0, 16.0, 50.0):
-        w = workloads.box(n_part_log2=18, n_side=128, soft_kpc_h=soft)
+        w = workloads.box(n_part_log2=18, n_side=128, soft_kpc_h=soft, radius_arcsec=0.1)
         g = GpuRun(w)
         t0 = time.perf_counter()
         out = g.run(rt.RT_FP32_KAHAN)
