@@ -168,6 +168,21 @@ rt_status rt_magnification(const rt_cosmology* cosmo, double z_source, int64_t n
 rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi,
                           double* pdf, double* moments, hipStream_t stream);
 
+/* Flexion of each bundle at z = chi_s (Sec. 6: flexion, the gradient of the shear, is the
+ * third-order lensing effect that ray bundles can carry).  With the ring offsets
+ * D_k = x_k - x_anchor = chi_s (r A e_k + 1/2 r^2 Dm(e_k, e_k)) + O(r^3), e_k = (cos 2 pi k / 8,
+ * sin 2 pi k / 8), Dm_ijl = d A_ij / d theta_l is read from the ring's harmonics 0 and 2 (the
+ * first- and third-order parts fall in harmonics 1 and 3): the least-squares second-order fit of
+ * the ring.  flex: device [4][n_bundles] = F1, F2 (F = grad kappa), G1, G2 (G = d gamma with
+ * d = d1 + i d2: d1 gamma1 - d2 gamma2, d2 gamma1 + d1 gamma2), in rad^-1, kappa and gamma read
+ * from A as in rt_magnification; dm: device [6][n_bundles] = Dm_111, Dm_112, Dm_122, Dm_211,
+ * Dm_212, Dm_222 (rad^-1), or NULL.  For a lens potential psi, Dm_ijl = -psi_ijl.  The second-
+ * order part is r / theta_lens of the ring offsets: pick the bundle radius (rt_build_bundles) so
+ * that it stays well above the trace's error on the offsets.  rays: device [8][9 n_bundles];
+ * radius: the radius given to rt_build_bundles. */
+rt_status rt_flexion(const rt_cosmology* cosmo, double z_source, int64_t n_bundles, double radius, const double* rays,
+                     double* flex, double* dm, hipStream_t stream);
+
 /* rt_mu_histogram for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): the same kernels and results, with the
  * per-call scratch (the bin weights and five sums) in a static per-device array of the library
@@ -255,13 +270,32 @@ rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, int32_t n_grid
  * the step that overshoots is replaced by the linear interpolation between the previous and
  * the current state at z = chi_s (all eight components).  A ray that has not reached chi_s
  * after max_steps keeps its last state and is flagged 8.  f_rk > 0, max_steps >= 1; the grid
- * must be isolated (RT_ERR_UNSUPPORTED for a periodic one) and leave the observer outside its
- * nodes, as for rt_trace_pm.  rays: device [8][9 n_bundles], in and
+ * gives the field everywhere; an isolated one must leave the observer outside its nodes, and for
+ * a periodic one the caller builds the bundles with the potential it wants at the observer, as
+ * for rt_trace_pm.  rays: device [8][9 n_bundles], in and
  * out (z on entry < chi_s); ray_flags: device [9 n_bundles] or NULL (1, 2, 4 as for rt_trace,
  * 8 as above); ray_steps: device int32 [9 n_bundles] or NULL, steps taken per ray. */
 rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const rt_pm_grid* grid,
                              const double* fields, int32_t n_int, double f_rk, int32_t max_steps, int64_t n_bundles,
                              double* rays, uint8_t* ray_flags, int32_t* ray_steps, hipStream_t stream);
+
+/* rt_trace_pm_lambda through a stack of grids along the line of sight (Sec. 5.2: the space
+ * between observer and source filled by cubes, each with its own Fourier grid; Sec. 3.4,
+ * eq. RKstepsize for the integrator).  Every field evaluation looks up the slab that holds its
+ * own x^3: slab k = [slab_bounds[k], slab_bounds[k + 1]) takes grid slab_grid[k] (-1 = no
+ * field); a point outside [slab_bounds[0], slab_bounds[n_slabs]) sees no field.  The fixed step
+ * is f_rk h / kz_0 with the grids' common spacing h (all grids must have the same h).
+ * grids: host [n_grids]; fields: host [n_grids] of device pointers to built fields; n_int as for
+ * rt_pm_eval (valid for every grid); slab_bounds: host [n_slabs + 1], finite, strictly
+ * increasing; slab_grid: host int32 [n_slabs], each in [-1, n_grids).  Isolated grids must
+ * leave the observer outside their nodes.  The host tables are copied to a device buffer that
+ * the call allocates and frees on the stream (the call waits for the copies).  Rays, flags,
+ * steps, f_rk and max_steps as for rt_trace_pm_lambda. */
+rt_status rt_trace_pm_lambda_slabs(const rt_cosmology* cosmo, double z_source, int32_t n_grids,
+                                   const rt_pm_grid* grids, const double* const* fields, int32_t n_int,
+                                   int32_t n_slabs, const double* slab_bounds, const int32_t* slab_grid, double f_rk,
+                                   int32_t max_steps, int64_t n_bundles, double* rays, uint8_t* ray_flags,
+                                   int32_t* ray_steps, hipStream_t stream);
 
 /* ---------------------------------------------------------------- tuning and introspection */
 

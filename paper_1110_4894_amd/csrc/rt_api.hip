@@ -745,6 +745,20 @@ rt_status rt_magnification(const rt_cosmology* cosmo, double z_source, int64_t n
   return RT_OK;
 }
 
+rt_status rt_flexion(const rt_cosmology* cosmo, double z_source, int64_t n_bundles, double radius, const double* rays,
+                     double* flex, double* dm, hipStream_t stream) {
+  rt_status st = check_cosmo(cosmo);
+  if (st != RT_OK) return st;
+  if (!std::isfinite(z_source) || !std::isfinite(radius)) return fail(RT_ERR_NONFINITE, "z_source or radius");
+  if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
+  if (!(radius > 0.0) || !(radius < 1e-2)) return fail(RT_ERR_INVALID_ARG, "radius must be in (0, 1e-2) rad");
+  if (n_bundles <= 0) return fail(RT_ERR_INVALID_ARG, "n_bundles must be > 0");
+  if (!rays || !flex) return fail(RT_ERR_INVALID_ARG, "rays or flex is NULL");
+  const double chi_s = comoving_distance(*cosmo, z_source);
+  RT_HIP(launch_flexion(chi_s, n_bundles, radius, rays, flex, dm, stream));
+  return RT_OK;
+}
+
 rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double log_lo, double log_hi, double* pdf,
                           double* moments, hipStream_t stream) {
   if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");
@@ -1102,12 +1116,74 @@ rt_status rt_trace_pm_lambda(const rt_cosmology* cosmo, double z_source, const r
   if (max_steps < 1) return fail(RT_ERR_INVALID_ARG, "max_steps must be >= 1");
   if (n_bundles < 0) return fail(RT_ERR_INVALID_ARG, "n_bundles < 0");
   if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
-  if (grid->periodic) return fail(RT_ERR_UNSUPPORTED, "rt_trace_pm_lambda takes an isolated grid");
-  if ((st = check_observer_outside(grid)) != RT_OK) return st;
+  if (!grid->periodic && (st = check_observer_outside(grid)) != RT_OK) return st;
   if (n_bundles == 0) return RT_OK;
   RT_HIP(launch_pm_trace_lambda(make_dev_cosmo(*cosmo), grid->origin, grid->h, grid->n, grid->periodic, fields, n_int,
                                 comoving_distance(*cosmo, z_source), f_rk, max_steps, rays, 9 * n_bundles, ray_flags,
                                 ray_steps, stream));
+  return RT_OK;
+}
+
+rt_status rt_trace_pm_lambda_slabs(const rt_cosmology* cosmo, double z_source, int32_t n_grids,
+                                   const rt_pm_grid* grids, const double* const* fields, int32_t n_int,
+                                   int32_t n_slabs, const double* slab_bounds, const int32_t* slab_grid, double f_rk,
+                                   int32_t max_steps, int64_t n_bundles, double* rays, uint8_t* ray_flags,
+                                   int32_t* ray_steps, hipStream_t stream) {
+  rt_status st;
+  if ((st = check_cosmo(cosmo)) != RT_OK) return st;
+  if (!std::isfinite(z_source)) return fail(RT_ERR_NONFINITE, "z_source is not finite");
+  if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
+  if (n_grids < 1 || !grids || !fields) return fail(RT_ERR_INVALID_ARG, "n_grids < 1, or grids or fields is NULL");
+  for (int i = 0; i < n_grids; ++i) {
+    if ((st = check_pm_grid(&grids[i])) != RT_OK) return fail(st, "grids[%d]: %s", i, g_err.c_str());
+    if ((st = check_n_int(&grids[i], n_int)) != RT_OK) return fail(st, "grids[%d]: %s", i, g_err.c_str());
+    if (!fields[i]) return fail(RT_ERR_INVALID_ARG, "fields[%d] is NULL", i);
+    if (!grids[i].periodic && (st = check_observer_outside(&grids[i])) != RT_OK)
+      return fail(st, "grids[%d]: %s", i, g_err.c_str());
+    if (grids[i].h != grids[0].h)
+      return fail(RT_ERR_INVALID_ARG, "grids[%d].h = %.17g differs from grids[0].h = %.17g", i, grids[i].h,
+                  grids[0].h);
+  }
+  if (n_slabs < 1 || !slab_bounds || !slab_grid)
+    return fail(RT_ERR_INVALID_ARG, "n_slabs < 1, or slab_bounds or slab_grid is NULL");
+  for (int k = 0; k <= n_slabs; ++k) {
+    if (!std::isfinite(slab_bounds[k])) return fail(RT_ERR_NONFINITE, "slab_bounds[%d] is not finite", k);
+    if (k > 0 && !(slab_bounds[k] > slab_bounds[k - 1]))
+      return fail(RT_ERR_INVALID_ARG, "slab_bounds not strictly increasing at %d", k);
+  }
+  for (int k = 0; k < n_slabs; ++k)
+    if (slab_grid[k] < -1 || slab_grid[k] >= n_grids)
+      return fail(RT_ERR_INVALID_ARG, "slab_grid[%d] = %d out of [-1, %d)", k, slab_grid[k], n_grids);
+  if (!std::isfinite(f_rk)) return fail(RT_ERR_NONFINITE, "f_rk is not finite");
+  if (!(f_rk > 0.0)) return fail(RT_ERR_INVALID_ARG, "f_rk must be > 0");
+  if (max_steps < 1) return fail(RT_ERR_INVALID_ARG, "max_steps must be >= 1");
+  if (n_bundles < 0) return fail(RT_ERR_INVALID_ARG, "n_bundles < 0");
+  if (n_bundles > 0 && !rays) return fail(RT_ERR_INVALID_ARG, "rays is NULL");
+  if (n_bundles == 0) return RT_OK;
+  std::vector<DevPmGrid> hg(n_grids);
+  for (int i = 0; i < n_grids; ++i) {
+    hg[i].n = grids[i].n;
+    for (int d = 0; d < 3; ++d) hg[i].origin[d] = grids[i].origin[d];
+    hg[i].h = grids[i].h;
+    hg[i].periodic = grids[i].periodic;
+    hg[i].fields = fields[i];
+  }
+  // scratch: grid table, then slab bounds, then slab grids
+  const size_t gbytes = ((sizeof(DevPmGrid) * n_grids + 255) / 256) * 256;
+  const size_t bbytes = ((sizeof(double) * (n_slabs + 1) + 255) / 256) * 256;
+  char* scratch = nullptr;
+  RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), gbytes + bbytes + sizeof(int32_t) * n_slabs, stream));
+  DevPmGrid* d_grids = reinterpret_cast<DevPmGrid*>(scratch);
+  double* d_bounds = reinterpret_cast<double*>(scratch + gbytes);
+  int32_t* d_sg = reinterpret_cast<int32_t*>(scratch + gbytes + bbytes);
+  RT_HIP(hipMemcpyAsync(d_grids, hg.data(), sizeof(DevPmGrid) * n_grids, hipMemcpyHostToDevice, stream));
+  RT_HIP(hipMemcpyAsync(d_bounds, slab_bounds, sizeof(double) * (n_slabs + 1), hipMemcpyHostToDevice, stream));
+  RT_HIP(hipMemcpyAsync(d_sg, slab_grid, sizeof(int32_t) * n_slabs, hipMemcpyHostToDevice, stream));
+  RT_HIP(hipStreamSynchronize(stream));   // the host staging above is pageable and local
+  RT_HIP(launch_pm_trace_lambda_slabs(make_dev_cosmo(*cosmo), d_grids, d_bounds, d_sg, n_slabs, grids[0].h, n_int,
+                                      comoving_distance(*cosmo, z_source), f_rk, max_steps, rays, 9 * n_bundles,
+                                      ray_flags, ray_steps, stream));
+  RT_HIP(hipFreeAsync(scratch, stream));
   return RT_OK;
 }
 

@@ -77,6 +77,8 @@ hipError_t launch_field_eval(DevCosmo c, const DevSet* set, bool fp64, int64_t n
                              double* grad, hipStream_t s);
 hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const double* rays, double* mu,
                                 double* jac, hipStream_t s);
+hipError_t launch_flexion(double chi_s, int64_t nb, double radius, const double* rays, double* flex, double* dm,
+                          hipStream_t s);
 // The static scratch of rt_mu_histogram_noalloc on the current device (its address is
 // looked up once per device) and the largest bin count it holds.
 hipError_t noalloc_scratch(double** out, int32_t* max_bins);
@@ -102,5 +104,9 @@ hipError_t launch_pm_trace(DevCosmo c, const DevPmGrid* grids, const int32_t* st
 hipError_t launch_pm_trace_lambda(DevCosmo c, const double origin[3], double h, int n, int periodic,
                                   const double* fields, int n_int, double chi_s, double f_rk, int32_t max_steps,
                                   double* rays, int64_t n_rays, uint8_t* flags, int32_t* steps, hipStream_t s);
+hipError_t launch_pm_trace_lambda_slabs(DevCosmo c, const DevPmGrid* grids, const double* bounds,
+                                        const int32_t* slab_grid, int32_t n_slabs, double h_rk, int n_int,
+                                        double chi_s, double f_rk, int32_t max_steps, double* rays, int64_t n_rays,
+                                        uint8_t* flags, int32_t* steps, hipStream_t s);
 
 }  // namespace rt

@@ -923,6 +923,77 @@ __global__ __launch_bounds__(256) void magnification_kernel(double chi_s, int64_
 }
 
 // ---------------------------------------------------------------------------
+// Bundle flexion (Sec. 6: flexion, the gradient of the shear, through ray
+// bundles).  About the anchor, the ring offsets are
+//   D_k = chi_s (r A e_k + 1/2 r^2 Dm(e_k, e_k)) + O(r^3),
+// e_k = (cos 2 pi k / 8, sin 2 pi k / 8), Dm_ijl = d A_ij / d theta_l.  Over the
+// eight ring rays the first- and third-order parts live in the harmonics 1 and
+// 3 only, so the harmonics 0 and 2 hold Dm alone:
+//   sum_k D_ik = 2 r^2 chi_s (Dm_i11 + Dm_i22),
+//   sum_k D_ik cos 2 phi_k = r^2 chi_s (Dm_i11 - Dm_i22),
+//   sum_k D_ik sin 2 phi_k = 2 r^2 chi_s Dm_i12
+// (cos 2 phi_k and sin 2 phi_k are exactly 0 or +-1).  F = grad kappa and
+// G = (d1 gamma1 - d2 gamma2, d2 gamma1 + d1 gamma2) with kappa, gamma read from
+// A as in magnification_kernel.  Same 9-lane layout as magnification_kernel.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void flexion_kernel(double chi_s, int64_t nb, double radius, const double* rays,
+                                                      double* flex, double* dm) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int seg = lane / 9, k = lane % 9;
+  const int64_t b = ((int64_t)blockIdx.x * 4 + wave) * 7 + seg;
+  const bool valid = (seg < 7) && (b < nb);
+  const int64_t N = 9 * nb;
+  const int64_t r = valid ? 9 * b + k : 0;
+  const double x = rays[N + r], y = rays[2 * N + r];
+  const int anchor = seg * 9;
+  const double dx = x - __shfl(x, anchor), dy = y - __shfl(y, anchor);
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (k > 0) {
+    const int q = (k - 1) & 3;   // 2 phi_k = q pi / 2 (mod 2 pi)
+    const double c2 = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+    const double s2 = q == 1 ? 1.0 : (q == 3 ? -1.0 : 0.0);
+    v[0] = dx;
+    v[1] = dy;
+    v[2] = dx * c2;
+    v[3] = dy * c2;
+    v[4] = dx * s2;
+    v[5] = dy * s2;
+  }
+#pragma unroll
+  for (int off = 1; off < 9; off <<= 1) {
+    const int src = (k + off < 9) ? lane + off : lane;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      const double o = __shfl(v[m], src);
+      if (k + off < 9) v[m] += o;
+    }
+  }
+  if (valid && k == 0) {
+    const double u = 1.0 / (radius * radius * chi_s);
+    const double tx = 0.5 * v[0] * u, ty = 0.5 * v[1] * u;   // Dm_x11 + Dm_x22, Dm_y11 + Dm_y22
+    const double ex = v[2] * u, ey = v[3] * u;               // Dm_x11 - Dm_x22, Dm_y11 - Dm_y22
+    const double d111 = 0.5 * (tx + ex), d122 = 0.5 * (tx - ex), d112 = 0.5 * v[4] * u;
+    const double d211 = 0.5 * (ty + ey), d222 = 0.5 * (ty - ey), d212 = 0.5 * v[5] * u;
+    // kappa = 1 - (A11 + A22) / 2, gamma1 = (A22 - A11) / 2, gamma2 = -(A12 + A21) / 2
+    const double dk1 = -0.5 * (d111 + d212), dk2 = -0.5 * (d112 + d222);
+    const double dg1_1 = 0.5 * (d212 - d111), dg1_2 = 0.5 * (d222 - d112);
+    const double dg2_1 = -0.5 * (d112 + d211), dg2_2 = -0.5 * (d122 + d212);
+    flex[b] = dk1;
+    flex[nb + b] = dk2;
+    flex[2 * nb + b] = dg1_1 - dg2_2;
+    flex[3 * nb + b] = dg1_2 + dg2_1;
+    if (dm) {
+      dm[b] = d111;
+      dm[nb + b] = d112;
+      dm[2 * nb + b] = d122;
+      dm[3 * nb + b] = d211;
+      dm[4 * nb + b] = d212;
+      dm[5 * nb + b] = d222;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Source-weighted histograms (Sec. 5.3, eq. weighthisto; the same weighting
 // for the shear distribution of Sec. 5.4): every bundle with mu > 0 has
 // weight 1/mu.  mode 0: value log10 mu, bins of width in mu; mode 1: value
@@ -1140,6 +1211,15 @@ hipError_t launch_magnification(double chi_s, int64_t nb, double radius, const d
   const int64_t waves = (nb + 6) / 7;
   hipLaunchKernelGGL(magnification_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, chi_s, nb, radius,
                      rays, mu, jac);
+  return hipGetLastError();
+}
+
+hipError_t launch_flexion(double chi_s, int64_t nb, double radius, const double* rays, double* flex, double* dm,
+                          hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  const int64_t waves = (nb + 6) / 7;
+  hipLaunchKernelGGL(flexion_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, chi_s, nb, radius, rays,
+                     flex, dm);
   return hipGetLastError();
 }
 

@@ -496,11 +496,13 @@ __global__ __launch_bounds__(256) void pm_trace_kernel(DevCosmo cz, const DevPmG
 }
 
 // The paper's own integrator (Sec. 3.4, eq. RKstepsize): classical RK4 in the
-// affine parameter with the fixed step f_RK h / kz_0 (h: the grid spacing,
-// kz_0: the ray's dz/dlambda at the start), repeated until z reaches chi_s;
-// the step that overshoots is replaced by the linear interpolation between
-// the previous and the current state at z = chi_s.  One ray per thread; a ray
-// that has not reached chi_s after max_steps is flagged 8.
+// affine parameter with the fixed step f_RK h / kz_0 (h: the Fourier-grid
+// spacing, kz_0: the ray's dz/dlambda at the start), repeated until z reaches
+// chi_s; the step that overshoots is replaced by the linear interpolation
+// between the previous and the current state at z = chi_s.  One ray per
+// thread; a ray that has not reached chi_s after max_steps is flagged 8.  The
+// field is a functor of the evaluation point: one grid everywhere, or the grid
+// of the slab along x^3 that holds the point (Sec. 5.2's stack of cubes).
 struct State8 {
   double t, x, y, z, kt, kx, ky, kz;
 };
@@ -511,34 +513,72 @@ __device__ __forceinline__ State8 axpy8(const State8& Y, double h, const State8&
 }
 
 template <int NI>
-__device__ __forceinline__ State8 rhs_lambda(const DevCosmo& c, const PmGrid& g, const double* fields,
-                                             const State8& Y, double& phi, double& a) {
+struct OneGridField {
+  PmGrid g;
+  const double* fields;
+  __device__ __forceinline__ void operator()(double x, double y, double z, double& phi, double& gx, double& gy,
+                                             double& gz) const {
+    pm_field<NI>(g, fields, x, y, z, phi, gx, gy, gz);
+  }
+};
+
+// bounds [n_slabs + 1] strictly increasing; slab k = [bounds[k], bounds[k + 1])
+// takes grid slab_grid[k] (none for -1); no field outside [bounds[0],
+// bounds[n_slabs]) (a NaN z included).
+template <int NI>
+struct SlabField {
+  const DevPmGrid* grids;
+  const double* bounds;
+  const int32_t* slab_grid;
+  int32_t n_slabs;
+  __device__ __forceinline__ void operator()(double x, double y, double z, double& phi, double& gx, double& gy,
+                                             double& gz) const {
+    phi = gx = gy = gz = 0.0;
+    if (!(z >= bounds[0] && z < bounds[n_slabs])) return;
+    int lo = 0, hi = n_slabs;   // bounds[lo] <= z < bounds[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (z >= bounds[mid])
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int gi = slab_grid[lo];
+    if (gi < 0) return;
+    const DevPmGrid d = grids[gi];
+    pm_field<NI>(PmGrid{d.n, d.origin[0], d.origin[1], d.origin[2], d.h, d.periodic}, d.fields, x, y, z, phi, gx, gy,
+                 gz);
+  }
+};
+
+template <class FieldAt>
+__device__ __forceinline__ State8 rhs_lambda(const DevCosmo& c, const FieldAt& field, const State8& Y, double& phi,
+                                             double& a) {
   double gx, gy, gz, At, Ax, Ay, Az;
-  pm_field<NI>(g, fields, Y.x, Y.y, Y.z, phi, gx, gy, gz);
+  field(Y.x, Y.y, Y.z, phi, gx, gy, gz);
   accel(c, Y.t, Y.kt, Y.kx, Y.ky, Y.kz, phi, gx, gy, gz, a, At, Ax, Ay, Az);
   return State8{Y.kt, Y.kx, Y.ky, Y.kz, -At, -Ax, -Ay, -Az};
 }
 
-template <int NI>
-__global__ __launch_bounds__(256) void pm_trace_lambda_kernel(DevCosmo cz, PmGrid g, const double* __restrict__ fields,
-                                                              double chi_s, double f_rk, int32_t max_steps,
-                                                              double* rays, int64_t N, uint8_t* flags,
-                                                              int32_t* steps_out) {
+template <class FieldAt>
+__global__ __launch_bounds__(256) void pm_trace_lambda_kernel(DevCosmo cz, FieldAt field, double h_rk, double chi_s,
+                                                              double f_rk, int32_t max_steps, double* rays, int64_t N,
+                                                              uint8_t* flags, int32_t* steps_out) {
   const int64_t ri = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ri >= N) return;
   State8 Y{rays[ri],         rays[N + ri],     rays[2 * N + ri], rays[3 * N + ri],
            rays[4 * N + ri], rays[5 * N + ri], rays[6 * N + ri], rays[7 * N + ri]};
-  const double dl = f_rk * g.h / Y.kz;
+  const double dl = f_rk * h_rk / Y.kz;
   uint8_t flag = 0;
   bool done = !(Y.z < chi_s);
   int32_t s = 0;
   for (; s < max_steps && !done; ++s) {
     double phi, a, unused_phi, unused_a;
-    const State8 k1 = rhs_lambda<NI>(cz, g, fields, Y, phi, a);
+    const State8 k1 = rhs_lambda(cz, field, Y, phi, a);
     if (fabs(phi) / a > 1e-2) flag |= 4;
-    const State8 k2 = rhs_lambda<NI>(cz, g, fields, axpy8(Y, 0.5 * dl, k1), unused_phi, unused_a);
-    const State8 k3 = rhs_lambda<NI>(cz, g, fields, axpy8(Y, 0.5 * dl, k2), unused_phi, unused_a);
-    const State8 k4 = rhs_lambda<NI>(cz, g, fields, axpy8(Y, dl, k3), unused_phi, unused_a);
+    const State8 k2 = rhs_lambda(cz, field, axpy8(Y, 0.5 * dl, k1), unused_phi, unused_a);
+    const State8 k3 = rhs_lambda(cz, field, axpy8(Y, 0.5 * dl, k2), unused_phi, unused_a);
+    const State8 k4 = rhs_lambda(cz, field, axpy8(Y, dl, k3), unused_phi, unused_a);
     State8 sum = axpy8(k1, 2.0, k2);
     sum = axpy8(sum, 2.0, k3);
     sum = axpy8(sum, 1.0, k4);
@@ -673,20 +713,50 @@ hipError_t launch_pm_trace_lambda(DevCosmo c, const double origin[3], double h, 
   const dim3 grid(blocks_for(n_rays, 256)), block(256);
   switch (n_int) {
     case 1:
-      hipLaunchKernelGGL(pm_trace_lambda_kernel<1>, grid, block, 0, s, c, g, fields, chi_s, f_rk, max_steps, rays,
-                         n_rays, flags, steps);
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<OneGridField<1>>, grid, block, 0, s, c, OneGridField<1>{g, fields}, h,
+                         chi_s, f_rk, max_steps, rays, n_rays, flags, steps);
       break;
     case 2:
-      hipLaunchKernelGGL(pm_trace_lambda_kernel<2>, grid, block, 0, s, c, g, fields, chi_s, f_rk, max_steps, rays,
-                         n_rays, flags, steps);
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<OneGridField<2>>, grid, block, 0, s, c, OneGridField<2>{g, fields}, h,
+                         chi_s, f_rk, max_steps, rays, n_rays, flags, steps);
       break;
     case 3:
-      hipLaunchKernelGGL(pm_trace_lambda_kernel<3>, grid, block, 0, s, c, g, fields, chi_s, f_rk, max_steps, rays,
-                         n_rays, flags, steps);
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<OneGridField<3>>, grid, block, 0, s, c, OneGridField<3>{g, fields}, h,
+                         chi_s, f_rk, max_steps, rays, n_rays, flags, steps);
       break;
     default:
-      hipLaunchKernelGGL(pm_trace_lambda_kernel<4>, grid, block, 0, s, c, g, fields, chi_s, f_rk, max_steps, rays,
-                         n_rays, flags, steps);
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<OneGridField<4>>, grid, block, 0, s, c, OneGridField<4>{g, fields}, h,
+                         chi_s, f_rk, max_steps, rays, n_rays, flags, steps);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pm_trace_lambda_slabs(DevCosmo c, const DevPmGrid* grids, const double* bounds,
+                                        const int32_t* slab_grid, int32_t n_slabs, double h_rk, int n_int,
+                                        double chi_s, double f_rk, int32_t max_steps, double* rays, int64_t n_rays,
+                                        uint8_t* flags, int32_t* steps, hipStream_t s) {
+  const dim3 grid(blocks_for(n_rays, 256)), block(256);
+  switch (n_int) {
+    case 1:
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<SlabField<1>>, grid, block, 0, s, c,
+                         SlabField<1>{grids, bounds, slab_grid, n_slabs}, h_rk, chi_s, f_rk, max_steps, rays, n_rays,
+                         flags, steps);
+      break;
+    case 2:
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<SlabField<2>>, grid, block, 0, s, c,
+                         SlabField<2>{grids, bounds, slab_grid, n_slabs}, h_rk, chi_s, f_rk, max_steps, rays, n_rays,
+                         flags, steps);
+      break;
+    case 3:
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<SlabField<3>>, grid, block, 0, s, c,
+                         SlabField<3>{grids, bounds, slab_grid, n_slabs}, h_rk, chi_s, f_rk, max_steps, rays, n_rays,
+                         flags, steps);
+      break;
+    default:
+      hipLaunchKernelGGL(pm_trace_lambda_kernel<SlabField<4>>, grid, block, 0, s, c,
+                         SlabField<4>{grids, bounds, slab_grid, n_slabs}, h_rk, chi_s, f_rk, max_steps, rays, n_rays,
+                         flags, steps);
       break;
   }
   return hipGetLastError();

@@ -61,10 +61,11 @@ class rt_pm_grid(C.Structure):
 
 
 EXPORTS = ["rt_comoving_distance", "rt_make_schedule", "rt_replica_step_sets", "rt_build_bundles", "rt_trace",
-           "rt_magnification", "rt_mu_histogram", "rt_mu_histogram_noalloc", "rt_shear_histogram", "rt_field_eval",
+           "rt_magnification", "rt_flexion", "rt_mu_histogram", "rt_mu_histogram_noalloc", "rt_shear_histogram", "rt_field_eval",
            "rt_plan_count", "rt_plan_describe",
            "rt_force_plan", "rt_set_grid_limit", "rt_autotune", "rt_enable_timing", "rt_last_trace_info", "rt_last_error",
-           "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda", "rt_sync"]
+           "rt_release_caches", "rt_pm_workspace_bytes", "rt_pm_build", "rt_pm_eval", "rt_trace_pm", "rt_trace_pm_lambda",
+           "rt_trace_pm_lambda_slabs", "rt_sync"]
 
 _lib = None
 
@@ -85,6 +86,7 @@ def load(path: str = LIB_PATH):
         "rt_build_bundles": (st, [p, p, i32, i64, p, d, p, p]),
         "rt_trace": (st, [p, d, p, i32, st, i32, i32, i64, p, p, p]),
         "rt_magnification": (st, [p, d, i64, d, p, p, p, p]),
+        "rt_flexion": (st, [p, d, i64, d, p, p, p, p]),
         "rt_mu_histogram": (st, [i64, p, i32, d, d, p, p, p]),
         "rt_mu_histogram_noalloc": (st, [i64, p, i32, d, d, p, p, p]),
         "rt_shear_histogram": (st, [i64, p, p, i32, d, d, p, p, p]),
@@ -104,6 +106,7 @@ def load(path: str = LIB_PATH):
         "rt_pm_eval": (st, [p, p, i32, i64, p, p, p, p]),
         "rt_trace_pm": (st, [p, d, i32, p, p, i32, i32, p, p, i32, i32, i64, p, p, p]),
         "rt_trace_pm_lambda": (st, [p, d, p, p, i32, d, i32, i64, p, p, p, p]),
+        "rt_trace_pm_lambda_slabs": (st, [p, d, i32, p, p, i32, i32, p, p, d, i32, i64, p, p, p, p]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -224,6 +227,11 @@ def rt_magnification(cosmo, z_source: float, n_bundles: int, radius: float, rays
                                    _dptr(mu), _dptr(jac), _stream(stream)))
 
 
+def rt_flexion(cosmo, z_source: float, n_bundles: int, radius: float, rays, flex, dm=None, stream=None):
+    _check(load().rt_flexion(C.byref(cosmo), float(z_source), int(n_bundles), float(radius), _dptr(rays),
+                             _dptr(flex), _dptr(dm), _stream(stream)))
+
+
 def rt_mu_histogram(n: int, mu, n_bins: int, log_lo: float, log_hi: float, pdf, moments, stream=None):
     _check(load().rt_mu_histogram(int(n), _dptr(mu), int(n_bins), float(log_lo), float(log_hi), _dptr(pdf),
                                   _dptr(moments), _stream(stream)))
@@ -332,3 +340,20 @@ def rt_trace_pm_lambda(cosmo, z_source: float, grid: rt_pm_grid, fields, n_int: 
     _check(load().rt_trace_pm_lambda(C.byref(cosmo), float(z_source), C.byref(grid), _dptr(fields), int(n_int),
                                      float(f_rk), int(max_steps), int(n_bundles), _dptr(rays), _dptr(ray_flags),
                                      _dptr(ray_steps), _stream(stream)))
+
+
+def rt_trace_pm_lambda_slabs(cosmo, z_source: float, grids, fields, n_int: int, slab_bounds, slab_grid,
+                             f_rk: float, max_steps: int, n_bundles: int, rays, ray_flags=None, ray_steps=None,
+                             stream=None):
+    """grids: list of rt_pm_grid; fields: the matching built field tensors; slab_bounds [n_slabs + 1];
+    slab_grid [n_slabs] (grid index per slab, -1 = no field)."""
+    garr = (rt_pm_grid * len(grids))(*grids)
+    farr = (C.c_void_p * len(fields))(*[_dptr(f) for f in fields])
+    b = np.ascontiguousarray(slab_bounds, dtype=np.float64)
+    sg = np.ascontiguousarray(slab_grid, dtype=np.int32)
+    if b.size != sg.size + 1:
+        raise ValueError("slab_bounds must hold one more entry than slab_grid")
+    _check(load().rt_trace_pm_lambda_slabs(C.byref(cosmo), float(z_source), len(grids), C.addressof(garr),
+                                           C.addressof(farr), int(n_int), int(sg.size), b.ctypes.data,
+                                           sg.ctypes.data, float(f_rk), int(max_steps), int(n_bundles), _dptr(rays),
+                                           _dptr(ray_flags), _dptr(ray_steps), _stream(stream)))

@@ -171,10 +171,34 @@ def test_pm_argument_errors(lib):
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 2, 0.5, 0, 2, fake) == -1
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, around, fake, 2, 0.5, 100, 2, fake) == -1
     assert _status(rt.rt_trace_pm_lambda, c, 0.5, g, fake, 9, 0.5, 100, 2, fake) == -1
-    # periodic boxes: smaller workspace (no padding), no traces
+    # periodic boxes: smaller workspace (no padding)
     pg = rt.pm_grid(32, (-1.0, -1.0, 999.0), 0.0625, periodic=True)
     assert rt.rt_pm_workspace_bytes(pg) == 32 * 32 ** 3 + 8 * 32
     bad = rt.pm_grid(32, (0, 0, 0), 0.1)
     bad.periodic = 2
     assert _status(rt.rt_pm_workspace_bytes, bad) == -1
-    assert _status(rt.rt_trace_pm_lambda, c, 0.5, pg, fake, 2, 0.5, 100, 2, fake) == -7
+    # the slab stack of the lambda integrator
+    sl = rt.rt_trace_pm_lambda_slabs
+    b2, s2 = [0.0, 100.0, 200.0], [0, -1]
+    assert _status(sl, c, 0.5, [pg], [fake], 2, [0.0], [], 0.5, 100, 2, fake) == -1                 # no slab
+    assert _status(sl, c, 0.5, [pg], [fake], 2, [0.0, 100.0, 100.0], s2, 0.5, 100, 2, fake) == -1   # not increasing
+    assert _status(sl, c, 0.5, [pg], [fake], 2, [0.0, float("inf"), 300.0], s2, 0.5, 100, 2, fake) == -3
+    assert _status(sl, c, 0.5, [pg], [fake], 2, b2, [1, 0], 0.5, 100, 2, fake) == -1                # no grid 1
+    assert "slab_grid" in rt.rt_last_error()
+    assert _status(sl, c, 0.5, [pg, around], [fake, fake], 2, b2, s2, 0.5, 100, 2, fake) == -1      # observer
+    coarse = rt.pm_grid(32, (-1.0, -1.0, 999.0), 0.125, periodic=True)
+    assert _status(sl, c, 0.5, [pg, coarse], [fake, fake], 2, b2, s2, 0.5, 100, 2, fake) == -1      # two spacings
+    assert ".h" in rt.rt_last_error()
+    assert _status(sl, c, 0.5, [pg], [fake], 2, b2, s2, 0.0, 100, 2, fake) == -1
+    assert _status(sl, c, 0.5, [pg], [fake], 9, b2, s2, 0.5, 100, 2, fake) == -1
+
+
+def test_flexion_argument_errors(lib):
+    """rt_flexion validates its arguments on the host, before any device call."""
+    c = rt.cosmology()
+    fake = 1 << 40
+    assert _status(rt.rt_flexion, c, 0.5, 0, 1e-8, fake, fake) == -1
+    assert _status(rt.rt_flexion, c, 0.5, 4, 0.0, fake, fake) == -1
+    assert _status(rt.rt_flexion, c, 0.5, 4, float("nan"), fake, fake) == -3
+    assert _status(rt.rt_flexion, c, 0.5, 4, 1e-8, fake, None) == -1
+    assert _status(rt.rt_flexion, c, -1.0, 4, 1e-8, fake, fake) == -1

@@ -307,3 +307,57 @@ def test_box_light_cone_through_periodic_replica_grids_matches_oracle():
     th = np.repeat(theta, 9, axis=1)
     defl = np.hypot(orays[1] - th[0] * chi_s, orays[2] - th[1] * chi_s)
     assert np.all(np.hypot(g_rays[1] - orays[1], g_rays[2] - orays[2]) <= 1e-7 * defl + 1e-12)
+
+
+def test_lambda_integrator_through_a_stack_of_replica_grids_matches_oracle():
+    """The paper's own integrator (Sec. 3.4, eq. RKstepsize) through the light cone of Sec. 5.2:
+    a 2^12-particle Zel'dovich box in 14 replicas, each on its own periodic 16^3 grid and each
+    looked up in its own slab [r L, (r + 1) L) of x^3, per field evaluation (f_RK = 2 and 1)."""
+    from paper_1110_4894_amd.runner import GpuRun
+    from tests.oracle_run import oracle_fields
+    w = wl.box(n_part_log2=12, n_side=4, n_steps=200)
+    w = wl.subsample(w, 5, 1, max_bundles=2)
+    f = w.fields[0]
+    L = f.replica_box
+    n, n_int = 16, 2
+    g = GpuRun(w)
+    dev = torch.device("cuda")
+    grids, fields, ofields = [], [], []
+    for r, s in enumerate(f.sets):
+        origin = np.array([-0.5 * L, -0.5 * L, r * L])
+        grid = rt.pm_grid(n, origin, L / n, periodic=True)
+        nb = rt.rt_pm_workspace_bytes(grid)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        fl = torch.empty((8, n, n, n), dtype=torch.float64, device=dev)
+        pset = rt.make_particle_set(g.fields[0]["sets"][r]["xyzm"], softening=s.softening)
+        rt.rt_pm_build(pset, grid, fl, ws, nb)
+        grids.append(grid)
+        fields.append(fl)
+        F = opm.periodic_field(opm.cic_deposit_periodic(s.xyz, s.m, origin, L / n, n), L / n)
+        ofields.append((F, opm.spline_y2_periodic(F, L / n), origin, L / n, True))
+    bounds = np.arange(len(grids) + 1) * L
+    slab_grid = np.arange(len(grids), dtype=np.int32)
+    c, chi_s, ofl, theta = oracle_fields(w)
+    assert bounds[-1] > chi_s
+    for f_rk in (2.0, 1.0):
+        g.build_bundles()
+        steps = torch.zeros(9 * g.n_bundles, dtype=torch.int32, device=dev)
+        rt.rt_trace_pm_lambda_slabs(g.cosmo, w.z_source, grids, fields, n_int, bounds, slab_grid, f_rk, 10 ** 6,
+                                    g.n_bundles, g.rays, g.flags, steps)
+        g.magnification()
+        torch.cuda.synchronize()
+        g_rays, g_mu = g.rays.cpu().numpy(), g.mu.cpu().numpy()
+        assert not g.flags.cpu().numpy().any()
+        orays = orc.build_bundles(c, ofl, theta, w.bundle_radius)
+        print("    [pm] oracle lambda trace through %d replica slabs, %d rays, f_RK = %g"
+              % (len(ofields), orays.shape[1], f_rk), flush=True)
+        orays, oflags, osteps = opm.trace_pm_lambda_slabs(c, chi_s, orays, ofields, bounds, slab_grid, L / n, n_int,
+                                                          f_rk, 10 ** 6)
+        omu, _ = orc.magnification(chi_s, orays, w.bundle_radius)
+        assert not oflags.any()
+        assert np.array_equal(steps.cpu().numpy(), osteps)
+        assert np.max(np.abs(g_mu / omu - 1)) < 1e-7
+        th = np.repeat(theta, 9, axis=1)
+        defl = np.hypot(orays[1] - th[0] * chi_s, orays[2] - th[1] * chi_s)
+        assert np.all(np.hypot(g_rays[1] - orays[1], g_rays[2] - orays[2]) <= 1e-7 * defl + 1e-12)
+        assert np.allclose(g_rays[3], chi_s, rtol=1e-13, atol=0)
