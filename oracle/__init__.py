@@ -20,7 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c to load instead (the sanitizer test's).
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -54,7 +55,8 @@ class _Field(C.Structure):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.environ.get("ORACLE_LIB") and (not os.path.exists(_LIB)
+                                                 or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         lib = C.CDLL(_LIB)
         d, p, i32, i64 = C.c_double, C.c_void_p, C.c_int32, C.c_int64

@@ -35,6 +35,15 @@ rt_status fail(rt_status st, const char* fmt, ...) {
   return st;
 }
 
+// A C caller may pass any int for an rt_precision, and reading an enum object
+// that holds no enumerator's value is undefined in C++: look at its bytes.
+bool valid_precision(const rt_precision& p) {
+  int32_t v;
+  static_assert(sizeof(p) == sizeof(v), "rt_precision is an int");
+  std::memcpy(&v, &p, sizeof(v));
+  return v == 0 || v == 1;   // RT_FP64, RT_FP32_KAHAN
+}
+
 #define RT_HIP(expr)                                                                       \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -645,7 +654,7 @@ rt_status rt_trace(const rt_cosmology* cosmo, double z_source, const rt_field* f
                    uint8_t* ray_flags, hipStream_t stream) {
   rt_status st = check_cosmo(cosmo);
   if (st != RT_OK) return st;
-  if (precision != RT_FP64 && precision != RT_FP32_KAHAN) return fail(RT_ERR_INVALID_ARG, "unknown precision");
+  if (!valid_precision(precision)) return fail(RT_ERR_INVALID_ARG, "unknown precision");
   if (!std::isfinite(z_source)) return fail(RT_ERR_NONFINITE, "z_source is not finite");
   if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
   if (n_bundles <= 0) return fail(RT_ERR_INVALID_ARG, "n_bundles must be > 0");
@@ -811,7 +820,7 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
   if (st != RT_OK) return st;
   if (!set) return fail(RT_ERR_INVALID_ARG, "set is NULL");
   if ((st = check_set(*set, 0, 0)) != RT_OK) return st;
-  if (precision != RT_FP64 && precision != RT_FP32_KAHAN) return fail(RT_ERR_INVALID_ARG, "unknown precision");
+  if (!valid_precision(precision)) return fail(RT_ERR_INVALID_ARG, "unknown precision");
   if (n < 0) return fail(RT_ERR_INVALID_ARG, "n < 0");
   if (n == 0) return RT_OK;
   if (!points || !phi || !grad) return fail(RT_ERR_INVALID_ARG, "points, phi or grad is NULL");
@@ -847,11 +856,11 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
 }
 
 int32_t rt_plan_count(rt_precision precision) {
-  return (precision == RT_FP64 || precision == RT_FP32_KAHAN) ? plan_count(precision == RT_FP64) : 0;
+  return valid_precision(precision) ? plan_count(precision == RT_FP64) : 0;
 }
 
 rt_status rt_plan_describe(rt_precision precision, int32_t id, rt_plan_info* info) {
-  if (precision != RT_FP64 && precision != RT_FP32_KAHAN) return fail(RT_ERR_INVALID_ARG, "unknown precision");
+  if (!valid_precision(precision)) return fail(RT_ERR_INVALID_ARG, "unknown precision");
   if (!info) return fail(RT_ERR_INVALID_ARG, "info is NULL");
   if (id < 0 || id >= plan_count(precision == RT_FP64)) return fail(RT_ERR_INVALID_ARG, "plan id %d out of range", id);
   *info = plan_info(precision == RT_FP64, id);
@@ -859,7 +868,7 @@ rt_status rt_plan_describe(rt_precision precision, int32_t id, rt_plan_info* inf
 }
 
 rt_status rt_force_plan(rt_precision precision, int32_t id) {
-  if (precision != RT_FP64 && precision != RT_FP32_KAHAN) return fail(RT_ERR_INVALID_ARG, "unknown precision");
+  if (!valid_precision(precision)) return fail(RT_ERR_INVALID_ARG, "unknown precision");
   if (id < -1 || id >= plan_count(precision == RT_FP64)) return fail(RT_ERR_INVALID_ARG, "plan id %d out of range", id);
   std::lock_guard<std::mutex> lk(g.mu);
   g.forced[precision == RT_FP64] = id;
@@ -878,7 +887,7 @@ rt_status rt_autotune(const rt_cosmology* cosmo, double z_source, const rt_field
                       const double* rays, int32_t* best_id, hipStream_t stream) {
   rt_status st = check_cosmo(cosmo);
   if (st != RT_OK) return st;
-  if (precision != RT_FP64 && precision != RT_FP32_KAHAN) return fail(RT_ERR_INVALID_ARG, "unknown precision");
+  if (!valid_precision(precision)) return fail(RT_ERR_INVALID_ARG, "unknown precision");
   if (!(z_source > 0.0)) return fail(RT_ERR_INVALID_ARG, "z_source must be > 0");
   if (n_bundles <= 0 || !rays) return fail(RT_ERR_INVALID_ARG, "n_bundles or rays");
   if (step_begin < 0 || n_probe_steps < 1) return fail(RT_ERR_INVALID_ARG, "bad probe window");

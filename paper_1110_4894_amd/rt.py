@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librt.so")
+# RT_LIB_PATH names another build of the library to load instead (the host-sanitizer test's).
+LIB_PATH = os.environ.get("RT_LIB_PATH") or os.path.join(_HERE, "librt.so")
 
 RT_OK = 0
 RT_FP64 = 0
