@@ -7,15 +7,17 @@ times with random shifts and rotations out to z_s = 0.5), 512 x 512 bundles
 softening 50 kpc/h; FP32 pair terms with Kahan sums, FP64 integration.
 
 One step = one pass of the hot path over one batch: a band of --band bundles
-(7168 = 1024 wavefront groups of 7 bundles) of the row-major bundle grid
-advanced through a window of --window RK4 steps
-(rt_trace with a step window, one captured graph per window).  A band's first
-window starts with bundle construction (rt_build_bundles) and its last window
-ends with the magnification (rt_magnification) and the source-weighted muPDF
-(rt_mu_histogram, 200 log bins); with the default 100-step window, 20 steps
-carry one band through the whole schedule.  Steps walk through the windows and
-then through the bands.  Inputs (particles, bundle directions) are resident in
-HBM before the timed region.
+(28672 = 4096 wavefront groups of 7 bundles, one 504-ray block per workgroup of
+a 512-workgroup launch) of the row-major bundle grid advanced through a window
+of --window RK4 steps (rt_trace with a step window, one captured graph per
+window).  A band's first window starts with bundle construction
+(rt_build_bundles) and its last window ends with the magnification
+(rt_magnification) and the source-weighted muPDF (rt_mu_histogram, 200 log
+bins); with the default 25-step window, 80 steps carry one band through the
+whole schedule.  Steps walk through the windows and then through the bands.
+The three band-end calls are also timed on their own (untimed region) and
+reported with their share of a band.  Inputs (particles, bundle directions) are
+resident in HBM before the timed region.
 
 Reported beside the timed value (untimed):
   * mixed vs FP64 on the GPU: a subsample of the band through the centre of the
@@ -69,8 +71,8 @@ FLOP_PER_PAIR = 59.0
 FLOP_DIRECT = 20.0
 # FP64 direct sum per ray-particle interaction (same count as the direct term).
 FLOP_FP64 = 20.0
-# HBM bytes per launch of the FP32 trace kernel on the default workload (one 7168-bundle band,
-# one 100-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
+# HBM bytes per launch of the FP32 trace kernel on the default workload (one 28672-bundle band,
+# one 25-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain copy kernel, keyed by trace_kernel_code_sha of the kernel they were taken on.
 MEASURED_TRAFFIC = {}
 
@@ -84,9 +86,11 @@ def parse():
                    choices=["box20", "box18", "nfw", "point", "batched", "nfw_pm", "box18_pm", "box20_pm",
                             "pm_study", "nfw_study", "soft_study"])
     p.add_argument("--band", type=int, default=0,
-                   help="bundles per step of the one-field workloads (0: 7168, i.e. 1024 groups of 7 bundles)")
+                   help="bundles per step of the one-field workloads (0: 28672 for the boxes, i.e. 4096 groups "
+                        "of 7 bundles; 7168 otherwise)")
     p.add_argument("--window", type=int, default=-1,
-                   help="RK4 steps per bench step (0: the whole schedule; default 100 for the boxes, 0 otherwise)")
+                   help="RK4 steps per bench step (0: the whole schedule; default 25 for the boxes, 40 for batched, "
+                        "0 otherwise)")
     p.add_argument("--side", type=int, default=0, help="batched: bundle grid side of every field (0: the "
                                                        "workload's own seeded 64/128/256)")
     p.add_argument("--precision", default="fp32k", choices=["fp32k", "fp64"])
@@ -112,9 +116,9 @@ def parse():
                    help="only copy a buffer of this many MiB (HBM counter calibration) and exit")
     a = p.parse_args()
     if a.band == 0:
-        a.band = 7168
+        a.band = 28672 if a.workload in ("box20", "box18") else 7168
     if a.window < 0:
-        a.window = 100 if a.workload in ("box20", "box18") else 0
+        a.window = {"box20": 25, "box18": 25, "batched": 40}.get(a.workload, 0)
     return a
 
 
@@ -325,6 +329,15 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
     rt.rt_enable_timing(False)
     elapsed = t1 - t0
     value = inter_total / elapsed
+    # the calls at a band's ends, on their own (untimed): bundle construction (with the potential
+    # at the observer), magnification and the muPDF
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    g.build_bundles()
+    g.magnification()
+    g.histogram()
+    torch.cuda.synchronize()
+    band_ends_ms = (time.perf_counter() - tb) * 1e3
     inter_per_bundle = inter_band / per_step
     # roofline of the trace kernel: launches of full windows only (a shorter last window
     # would weigh the average otherwise)
@@ -340,7 +353,7 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
     plan_used = rt.rt_last_trace_info()["plan_id"]
     code_sha = trace_kernel_code_sha(rt.rt_plan_describe(prec, plan_used), prec == rt.RT_FP64)
     m = MEASURED_TRAFFIC.get(code_sha)
-    traffic = (m["read"] + m["write"]) if (m and a.workload == "box20" and a.band == 7168 and win == 100
+    traffic = (m["read"] + m["write"]) if (m and a.workload == "box20" and a.band == 28672 and win == 25
                                            and prec == rt.RT_FP32_KAHAN) else None
     prec_name = "fp64" if prec == rt.RT_FP64 else "fp32 pair terms with Kahan sums, fp64 integration"
     result = {
@@ -354,6 +367,8 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
                    "parallelism": "single GPU", "plan": tuned},
         "bundles_per_s": value / inter_per_bundle,
         "interactions_per_bundle": inter_per_bundle,
+        "band_ends": {"ms": band_ends_ms, "calls": "rt_build_bundles + rt_magnification + rt_mu_histogram",
+                      "share_of_band": band_ends_ms / (n_win * elapsed / max(a.steps, 1) * 1e3 + band_ends_ms)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch (read + write)",
                      "kernel_code_sha": code_sha,
