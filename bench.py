@@ -74,7 +74,10 @@ FLOP_FP64 = 20.0
 # HBM bytes per launch of the FP32 trace kernel on the default workload (one 28672-bundle band,
 # one 25-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain copy kernel, keyed by trace_kernel_code_sha of the kernel they were taken on.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 33912209.1 KiB x 1.9999, WRITE_SIZE 3920799.5 KiB x 1.0
+    "be6637116d00a4f5": {"read": 69448578123.0, "write": 4014898688.0, "plan": 4},
+}
 
 
 def parse():
@@ -447,14 +450,15 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not a.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(a, w, bands[0], windows[0], workloads)
+        result["cpu_baseline"] = cpu_baseline(a, w, bands[0], (windows[0][0], n_rk), workloads)
     print(json.dumps(result), flush=True)
 
 
 def cpu_baseline(a, w, band, window, workloads):
-    """The FP64 oracle on a bounded sample of the first band: a few bundles through the first
-    window of the schedule, on all host threads (as many bundles as threads, nine rays each),
-    and one bundle on one thread."""
+    """The FP64 oracle on a bounded sample of the first band: a few bundles from the start of the
+    schedule through as many RK4 steps as fit ~15 s (window = (first step, last step allowed)),
+    on all host threads (as many bundles as threads, nine rays each), and one bundle on one
+    thread (~12 s)."""
     import oracle as orc
     from tests.oracle_run import oracle_fields
     s0, s1 = window
