@@ -113,8 +113,9 @@ def parse():
                         "for box20)")
     p.add_argument("--pm-nint", type=int, default=2, help="App. B interpolation nodes on each side (nfw_pm)")
     p.add_argument("--pm-frk", type=float, default=0.0,
-                   help="nfw_pm: > 0 integrates in the affine parameter with the step f_RK h / kz_0 (eq. RKstepsize) "
-                        "instead of the z nodes")
+                   help="nfw_pm, box18_pm, box20_pm: > 0 integrates in the affine parameter with the step "
+                        "f_RK h / kz_0 (eq. RKstepsize) instead of the z nodes (the boxes: through the replica grids "
+                        "as a slab stack)")
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="only copy a buffer of this many MiB (HBM counter calibration) and exit")
     a = p.parse_args()
@@ -341,6 +342,13 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
     g.histogram()
     torch.cuda.synchronize()
     band_ends_ms = (time.perf_counter() - tb) * 1e3
+    # the bundle flexion of the band (Sec. 6), timed alone on the same rays
+    flex = torch.empty((4, g.n_bundles), dtype=torch.float64, device=dev)
+    tb = time.perf_counter()
+    rt.rt_flexion(g.cosmo, w.z_source, g.n_bundles, g.radius, g.rays, flex)
+    torch.cuda.synchronize()
+    flexion_ms = (time.perf_counter() - tb) * 1e3
+    del flex
     inter_per_bundle = inter_band / per_step
     # roofline of the trace kernel: launches of full windows only (a shorter last window
     # would weigh the average otherwise)
@@ -372,6 +380,7 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         "interactions_per_bundle": inter_per_bundle,
         "band_ends": {"ms": band_ends_ms, "calls": "rt_build_bundles + rt_magnification + rt_mu_histogram",
                       "share_of_band": band_ends_ms / (n_win * elapsed / max(a.steps, 1) * 1e3 + band_ends_ms)},
+        "flexion_ms": flexion_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic, "traffic_unit": "HBM bytes per launch (read + write)",
                      "kernel_code_sha": code_sha,
@@ -650,10 +659,20 @@ def bench_box_pm(a, torch, rt, workloads, GpuRun, dev):
     pdf = torch.empty(200, dtype=torch.float64, device=dev)
     mom = torch.empty(6, dtype=torch.float64, device=dev)
 
+    bounds = np.arange(len(grids) + 1) * L
+    steps_t = torch.zeros(9 * nb, dtype=torch.int32, device=dev)
+
     def one_step():
         g.build_bundles()
-        rt.rt_trace_pm(g.cosmo, w.z_source, grids, fields, a.pm_nint, nodes, 0, len(nodes) - 1, nb, g.rays, g.flags,
-                       step_grid=step_grid)
+        if a.pm_frk > 0:
+            # the paper's integrator (Sec. 3.4, eq. RKstepsize) through the replica stack, each field
+            # evaluation taking the grid of the replica that holds it (Sec. 5.2)
+            rt.rt_trace_pm_lambda_slabs(g.cosmo, w.z_source, grids, fields, a.pm_nint, bounds,
+                                        np.arange(len(grids), dtype=np.int32), a.pm_frk, 1 << 30, nb, g.rays,
+                                        g.flags, steps_t)
+        else:
+            rt.rt_trace_pm(g.cosmo, w.z_source, grids, fields, a.pm_nint, nodes, 0, len(nodes) - 1, nb, g.rays,
+                           g.flags, step_grid=step_grid)
         g.magnification()
         rt.rt_mu_histogram(nb, g.mu, 200, -0.1, 0.3, pdf, mom)
 
@@ -670,16 +689,19 @@ def bench_box_pm(a, torch, rt, workloads, GpuRun, dev):
     elapsed = time.perf_counter() - t0
     mu_pm = g.mu.cpu().numpy()
     m = mom.cpu().numpy()
-    ray_stages = 9.0 * nb * 4 * (len(nodes) - 1)
+    n_rk = float(steps_t.double().mean()) if a.pm_frk > 0 else float(len(nodes) - 1)
+    ray_stages = 9.0 * nb * 4 * n_rk
+    integ = ("RK4 in the affine parameter (f_RK = %g), each field evaluation taking the grid of its replica"
+             % a.pm_frk) if a.pm_frk > 0 else "RK4 over the z nodes"
     result = {
         "metric": "bundles/s through the particle-mesh field", "value": nb * a.steps / elapsed, "unit": "bundles/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * elapsed / a.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc + "; every bundle of the grid, each replica on a periodic %d^3 particle-mesh grid "
-                               "(h = %.3f Mpc), App. B with n_int = %d, RK4 over the z nodes; one step = %d bundles"
-                               % (n, L / n, a.pm_nint, nb),
+                               "(h = %.3f Mpc), App. B with n_int = %d, %s; one step = %d bundles"
+                               % (n, L / n, a.pm_nint, integ, nb),
                    "name": a.workload, "grid": n, "h_mpc": L / n, "n_int": a.pm_nint, "replicas": len(grids),
-                   "rk4_steps": len(nodes) - 1},
+                   "f_rk": a.pm_frk, "rk4_steps": n_rk},
         "ray_stages_per_s": ray_stages * a.steps / elapsed,
         "pm_build_ms_all_replicas": build_ms,
         "mu_pdf_moments": {"mean_w": float(m[1]), "sigma_w": float(m[2]), "n_nonpositive": int(m[3]),

@@ -224,3 +224,52 @@ def test_set_beyond_32bit_offsets():
         assert np.all(np.abs(gg - ref_g) <= tol * scale + 1e-30), prec
     del xyzm
     torch.cuda.empty_cache()
+
+
+def test_benchmark_launch_against_the_oracle():
+    """The launch bench.py times by default: the first 28672-bundle band of the 2^20 box's
+    512 x 512 grid through the first 25-step window, with the plan the autotuner picks for it
+    (one wavefront per 7 bundles, 1152-particle tiles, 512 workgroups).  16 seeded bundles of the
+    band against the oracle traced through the same window: positions and directions, each
+    relative to its change from the straight ray (a straight ray keeps x = (kx / kz) z).  (The
+    bundles' own lensing signal, the ring-minus-anchor offsets, is still below 1e-12 Mpc this
+    close to the observer; the whole-schedule tests compare it through mu.)"""
+    from paper_1110_4894_amd.runner import GpuRun
+    _say("building the 2^20 box")
+    w = wl.box(n_part_log2=20, n_side=512)
+    f = w.fields[0]
+    band, window = 28672, 25
+    wb = _with_theta(w, [f.theta[:, :band]])
+    plans = [i for i in range(rt.rt_plan_count(FP32K))
+             if rt.rt_plan_describe(FP32K, i)["waves_per_group"] == 1
+             and rt.rt_plan_describe(FP32K, i)["tile"] == 1152 and rt.rt_plan_describe(FP32K, i)["waves_per_block"] == 8]
+    assert plans
+    rt.rt_force_plan(FP32K, plans[0])
+    try:
+        _say("gpu fp32k: %d bundles, RK4 steps [0, %d)" % (band, window))
+        g = GpuRun(wb)
+        g.build_bundles()
+        g.trace(FP32K, 0, window)
+        torch.cuda.synchronize()
+        info = rt.rt_last_trace_info()
+        assert info["plan_id"] == plans[0] and info["grid_blocks"] == 512
+        rays = g.rays.cpu().numpy()
+        assert not g.flags.cpu().numpy().any()
+    finally:
+        rt.rt_force_plan(FP32K, -1)
+    idx = np.sort(np.random.default_rng(2811).choice(band, 16, replace=False))
+    ws = _with_theta(w, [f.theta[:, idx]])
+    _say("oracle: 16 bundles, RK4 steps [0, %d)" % window)
+    o = oracle_run(ws, step_begin=0, step_end=window)
+    c, _, ofields, theta = o["cosmo"], o["chi_s"], o["fields"], o["theta"]
+    r0 = orc.build_bundles(c, ofields, theta, w.bundle_radius)
+    got = rays[:, (9 * idx[:, None] + np.arange(9)).ravel()]
+    want = o["rays"]
+    assert np.array_equal(got[3], want[3])                      # both on the window's last node
+    z = want[3]
+    for comp, kc in ((1, 5), (2, 6)):
+        straight = r0[kc] / r0[7] * z
+        defl = want[comp] - straight
+        assert np.all(np.abs(got[comp] - want[comp]) <= 1e-4 * np.abs(defl) + 1e-13)
+        bend = want[kc] / want[7] - r0[kc] / r0[7]
+        assert np.all(np.abs(got[kc] / got[7] - want[kc] / want[7]) <= 1e-4 * np.abs(bend) + 1e-16)

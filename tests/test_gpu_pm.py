@@ -361,3 +361,59 @@ def test_lambda_integrator_through_a_stack_of_replica_grids_matches_oracle():
         defl = np.hypot(orays[1] - th[0] * chi_s, orays[2] - th[1] * chi_s)
         assert np.all(np.hypot(g_rays[1] - orays[1], g_rays[2] - orays[2]) <= 1e-7 * defl + 1e-12)
         assert np.allclose(g_rays[3], chi_s, rtol=1e-13, atol=0)
+
+
+def test_lambda_integrator_through_a_stack_of_isolated_cubes_matches_oracle():
+    """Sec. 5.2's prism: cubes cut along the line of sight, each on its own zero-padded grid (the
+    field of the structure within the cube only), traced by the lambda-stepping RK4 with each
+    field evaluation taking the grid of its cube's slab (and none between the last node of a
+    cube and the next cube, where the isolated grid has no nodes)."""
+    c, oc = rt.cosmology(), orc.cosmo()
+    z_s = 0.02
+    n, h = 16, 0.25
+    L = n * h
+    rng = np.random.default_rng(52)
+    dev = torch.device("cuda")
+    grids, fields, ogrids = [], [], []
+    for k in range(3):
+        z0 = 20.0 + k * L
+        origin = np.array([-0.5 * L, -0.5 * L, z0])
+        xyz = np.array([0.2 - 0.2 * k, 0.25, z0 + 0.5 * L]) + rng.normal(size=(300, 3)) * 0.3
+        xyz[:, 2] = np.clip(xyz[:, 2], z0 + 0.1, z0 + L - 0.6)
+        m = np.full(300, 3e12)
+        grid, fl, _ = _build(xyz, m, 0.01, n, origin, h)
+        grids.append(grid)
+        fields.append(fl)
+        F = opm.isolated_field(opm.cic_deposit(xyz, m, origin, h, n), h, 0.01)
+        ogrids.append((F, opm.z_second_derivatives(F, h), origin, h, False))
+    bounds = 20.0 + np.arange(4) * L
+    slab_grid = np.arange(3, dtype=np.int32)
+    theta_h = np.array([[0.2 / 24, -0.1 / 24], [0.25 / 24, 0.3 / 24]])
+    radius = 0.05 * np.pi / 180 / 3600
+    nb = theta_h.shape[1]
+    chi_s = rt.rt_comoving_distance(c, z_s)
+    nodes = np.array([0.0, chi_s])
+    empty = rt.FieldTable([{"sets": [], "z_nodes": nodes, "step_set": np.full(1, -1, np.int32), "bundle_offset": 0,
+                            "n_bundles": nb}])
+    ochi = orc.comoving_distance(oc, z_s)
+    of = orc.Field([], np.array([0.0, ochi]), np.full(1, -1, np.int32), 0, nb)
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    rt.rt_build_bundles(c, empty, nb, torch.from_numpy(theta_h).to(dev), radius, rays)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    steps = torch.zeros(9 * nb, dtype=torch.int32, device=dev)
+    rt.rt_trace_pm_lambda_slabs(c, z_s, grids, fields, 2, bounds, slab_grid, 1.0, 10 ** 6, nb, rays, flags, steps)
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    rt.rt_magnification(c, z_s, nb, radius, rays, mu, None)
+    torch.cuda.synchronize()
+    print("    [pm] oracle lambda trace through 3 isolated cubes", flush=True)
+    orays = orc.build_bundles(oc, [of], theta_h, radius)
+    orays, oflags, osteps = opm.trace_pm_lambda_slabs(oc, ochi, orays, ogrids, bounds, slab_grid, h, 2, 1.0, 10 ** 6)
+    omu, _ = orc.magnification(ochi, orays, radius)
+    assert not oflags.any() and not flags.cpu().numpy().any()
+    assert np.array_equal(steps.cpu().numpy(), osteps)
+    g = rays.cpu().numpy()
+    th = np.repeat(theta_h, 9, axis=1)
+    defl = np.hypot(orays[1] - th[0] * ochi, orays[2] - th[1] * ochi)
+    assert defl.min() > 1e-6                         # the rays are deflected
+    assert np.max(np.abs(mu.cpu().numpy() / omu - 1)) < 1e-7
+    assert np.all(np.hypot(g[1] - orays[1], g[2] - orays[2]) <= 1e-7 * defl + 1e-12)
