@@ -230,7 +230,7 @@ def zeldovich_positions(n_mesh: int, box: float, rng: np.random.Generator, n_ind
     QX, QY, QZ = np.meshgrid(q, q, q, indexing="ij")
     pos = np.empty((n_mesh ** 3, 3))
     for i, (K, Q) in enumerate(((KX, QX), (KY, QY), (KZ, QZ))):
-        s = np.fft.irfftn(1j * K / k2 * dk, s=(n_mesh,) * 3)
+        s = np.fft.irfftn(1j * K / k2 * dk, s=(n_mesh,) * 3, axes=(0, 1, 2))
         pos[:, i] = np.mod((Q + s).ravel(), box)
     return pos
 

@@ -265,7 +265,7 @@ def test_benchmark_launch_against_the_oracle():
     r0 = orc.build_bundles(c, ofields, theta, w.bundle_radius)
     got = rays[:, (9 * idx[:, None] + np.arange(9)).ravel()]
     want = o["rays"]
-    assert np.array_equal(got[3], want[3])                      # both on the window's last node
+    assert np.allclose(got[3], want[3], rtol=1e-13, atol=0)   # both on the window's last node (own schedules)
     z = want[3]
     for comp, kc in ((1, 5), (2, 6)):
         straight = r0[kc] / r0[7] * z
