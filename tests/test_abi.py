@@ -121,7 +121,7 @@ def test_argument_errors(lib):
     assert _status(rt.rt_mu_histogram, 10, fake, 0, -0.1, 0.3, fake, fake) == -1
     assert _status(rt.rt_mu_histogram, 10, fake, 10, 0.3, -0.1, fake, fake) == -1
     assert _status(rt.rt_force_plan, 0, 99) == -1
-    assert rt.rt_plan_count(0) >= 1 and rt.rt_plan_count(1) >= 1
+    assert rt.rt_plan_count(0) >= 1 and rt.rt_plan_count(1) >= 1 and rt.rt_plan_count(7) == 0
     info = rt.rt_plan_describe(1, 0)
     assert info["rays_per_block"] == 63 * info["waves_per_block"] // info["waves_per_group"]
 
