@@ -272,7 +272,7 @@ template <bool EQUAL, bool DETECT, bool EXCLUDE>
 __device__ __forceinline__ bool tile_moments(const float4* tile, const float2* tlo, int rounds, int l, float ex,
                                              float ey, float e2, float thr, float (&a)[kMom]) {
   bool any_near = false;
-#pragma unroll 4
+#pragma unroll 8
   for (int i = 0; i < rounds; ++i)
     any_near |= moment_terms<EQUAL, DETECT, EXCLUDE>(tile[9 * i + l], tlo[9 * i + l], ex, ey, e2, thr, a);
   return any_near;
@@ -1107,7 +1107,8 @@ struct PlanShape {
 // two workgroups of 8 wavefronts (four per SIMD, 128 registers) or three of 4
 // (three per SIMD, 168 registers) fit a compute unit.
 constexpr PlanShape kPlans32[] = {{8, 1, 576, 4}, {8, 2, 576, 4}, {8, 4, 576, 4}, {8, 8, 288, 4},
-                                  {8, 1, 1152, 4}, {8, 2, 1152, 4}, {4, 1, 576, 3}, {4, 4, 288, 3}};
+                                  {8, 1, 1152, 4}, {8, 2, 1152, 4}, {4, 1, 576, 3}, {4, 4, 288, 3},
+                                  {8, 1, 2304, 4}};
 constexpr PlanShape kPlans64[] = {{8, 1, 128, 4}, {8, 2, 128, 4}, {8, 4, 128, 4},
                                   {8, 8, 64, 4},  {4, 1, 128, 4}, {4, 4, 128, 4}};
 constexpr int kNumPlans32 = sizeof(kPlans32) / sizeof(kPlans32[0]);
