@@ -75,8 +75,10 @@ FLOP_FP64 = 20.0
 # one 25-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain copy kernel, keyed by trace_kernel_code_sha of the kernel they were taken on.
 MEASURED_TRAFFIC = {
-    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 33912209.1 KiB x 1.9999, WRITE_SIZE 3920799.5 KiB x 1.0
-    "be6637116d00a4f5": {"read": 69448578123.0, "write": 4014898688.0, "plan": 4},
+    # trace_kernel<false, 8, 1, 2304, 4>: FETCH_SIZE 36839319.7 KiB x 1.9999, WRITE_SIZE 4132780.7 KiB x 1.0
+    "806a9ff206f12bf2": {"read": 75442978572.0, "write": 4231967392.0, "plan": 8},
+    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 40900581.1 KiB x 1.9999, WRITE_SIZE 3924915.7 KiB x 1.0
+    "2ea94e3e9d846031": {"read": 83760006742.0, "write": 4019113632.0, "plan": 4},
 }
 
 
