@@ -50,6 +50,25 @@ bool valid_precision(const rt_precision& p) {
     if (e_ != hipSuccess) return fail(RT_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// A stream-ordered scratch allocation that is freed on every return path (an
+// argument or device error after the allocation included).
+struct StreamScratch {
+  void* p = nullptr;
+  hipStream_t s;
+  explicit StreamScratch(hipStream_t st) : s(st) {}
+  StreamScratch(const StreamScratch&) = delete;
+  StreamScratch& operator=(const StreamScratch&) = delete;
+  hipError_t alloc(size_t bytes) { return hipMallocAsync(&p, bytes, s); }
+  hipError_t release() {
+    const hipError_t e = p ? hipFreeAsync(p, s) : hipSuccess;
+    p = nullptr;
+    return e;
+  }
+  ~StreamScratch() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
 // ---------------------------------------------------------------- constants and background
 // GM_sun (IAU 2012 nominal), c (exact), 1 Mpc = 3.0856775814913673e22 m (IAU 2015).
 constexpr double kGMsun = 1.32712440018e20;
@@ -615,8 +634,9 @@ rt_status rt_build_bundles(const rt_cosmology* cosmo, const rt_field* fields, in
   // scratch: [n] DevSet, then doubles: [3] origin point, [n] phi, [3n] grad
   const size_t set_bytes = sizeof(DevSet) * n;
   const size_t dbl = 3 + n + 3 * n;
-  void* scratch = nullptr;
-  RT_HIP(hipMallocAsync(&scratch, set_bytes + sizeof(double) * dbl, stream));
+  StreamScratch sc(stream);
+  RT_HIP(sc.alloc(set_bytes + sizeof(double) * dbl));
+  void* scratch = sc.p;
   DevSet* d_sets = static_cast<DevSet*>(scratch);
   double* d_pt = reinterpret_cast<double*>(static_cast<char*>(scratch) + set_bytes);
   double* d_phi = d_pt + 3;
@@ -645,7 +665,7 @@ rt_status rt_build_bundles(const rt_cosmology* cosmo, const rt_field* fields, in
     RT_HIP(launch_field_eval(dc, d_sets + i, true, 1, d_pt, d_phi + i, d_grad + 3 * i, stream));
     RT_HIP(launch_bundles(dc, d_phi + i, F.bundle_offset, F.n_bundles, n_bundles, theta, radius, rays, stream));
   }
-  RT_HIP(hipFreeAsync(scratch, stream));
+  RT_HIP(sc.release());
   return RT_OK;
 }
 
@@ -776,10 +796,11 @@ rt_status rt_mu_histogram(int64_t n, const double* mu, int32_t n_bins, double lo
   if (n_bins < 1 || n_bins > 1 << 16) return fail(RT_ERR_INVALID_ARG, "n_bins must be in [1, 65536]");
   if (!std::isfinite(log_lo) || !std::isfinite(log_hi)) return fail(RT_ERR_NONFINITE, "histogram range");
   if (!(log_hi > log_lo)) return fail(RT_ERR_INVALID_ARG, "log_hi must exceed log_lo");
-  void* work = nullptr;
-  RT_HIP(hipMallocAsync(&work, sizeof(double) * (n_bins + 8), stream));
-  RT_HIP(launch_histogram(n, mu, nullptr, 0, n_bins, log_lo, log_hi, pdf, moments, static_cast<double*>(work), stream));
-  RT_HIP(hipFreeAsync(work, stream));
+  StreamScratch work(stream);
+  RT_HIP(work.alloc(sizeof(double) * (n_bins + 8)));
+  RT_HIP(launch_histogram(n, mu, nullptr, 0, n_bins, log_lo, log_hi, pdf, moments, static_cast<double*>(work.p),
+                          stream));
+  RT_HIP(work.release());
   return RT_OK;
 }
 
@@ -807,10 +828,10 @@ rt_status rt_shear_histogram(int64_t n, const double* mu, const double* jac, int
   if (n_bins < 1 || n_bins > 1 << 16) return fail(RT_ERR_INVALID_ARG, "n_bins must be in [1, 65536]");
   if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(RT_ERR_NONFINITE, "histogram range");
   if (!(hi > lo)) return fail(RT_ERR_INVALID_ARG, "hi must exceed lo");
-  void* work = nullptr;
-  RT_HIP(hipMallocAsync(&work, sizeof(double) * (n_bins + 8), stream));
-  RT_HIP(launch_histogram(n, mu, jac, 1, n_bins, lo, hi, pdf, moments, static_cast<double*>(work), stream));
-  RT_HIP(hipFreeAsync(work, stream));
+  StreamScratch work(stream);
+  RT_HIP(work.alloc(sizeof(double) * (n_bins + 8)));
+  RT_HIP(launch_histogram(n, mu, jac, 1, n_bins, lo, hi, pdf, moments, static_cast<double*>(work.p), stream));
+  RT_HIP(work.release());
   return RT_OK;
 }
 
@@ -840,8 +861,9 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
   // scratch: DevSet, its equal-mass flag, then (256-byte aligned) the FP32 copy
   const size_t flag_off = ((sizeof(DevSet) + 7) / 8) * 8;
   const size_t p32_off = ((flag_off + sizeof(int32_t) + 255) / 256) * 256;
-  void* scratch = nullptr;
-  RT_HIP(hipMallocAsync(&scratch, p32_off + p32_bytes, stream));
+  StreamScratch sc(stream);
+  RT_HIP(sc.alloc(p32_off + p32_bytes));
+  void* scratch = sc.p;
   DevSet* d_set = static_cast<DevSet*>(scratch);
   float4* p32 = reinterpret_cast<float4*>(static_cast<char*>(scratch) + p32_off);
   hs.p32 = p32_bytes ? p32 : nullptr;
@@ -851,7 +873,7 @@ rt_status rt_field_eval(const rt_cosmology* cosmo, const rt_particle_set* set, r
   RT_HIP(launch_prepare_sets(d_set, 1, stream));
   if (set->n > 0) RT_HIP(launch_convert_set(d_set, set->xyzm, hs.p32, set->n, stream));
   RT_HIP(launch_field_eval(dc, d_set, fp64, n, points, phi, grad, stream));
-  RT_HIP(hipFreeAsync(scratch, stream));
+  RT_HIP(sc.release());
   return RT_OK;
 }
 
@@ -1095,8 +1117,9 @@ rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, int32_t n_grid
   // scratch: grid table, then nodes, then step grids
   const size_t gbytes = ((sizeof(DevPmGrid) * n_grids + 255) / 256) * 256;
   const size_t nbytes = ((sizeof(double) * (n_steps + 1) + 255) / 256) * 256;
-  char* scratch = nullptr;
-  RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), gbytes + nbytes + sizeof(int32_t) * n_steps, stream));
+  StreamScratch sc(stream);
+  RT_HIP(sc.alloc(gbytes + nbytes + sizeof(int32_t) * n_steps));
+  char* scratch = static_cast<char*>(sc.p);
   DevPmGrid* d_grids = reinterpret_cast<DevPmGrid*>(scratch);
   double* d_nodes = reinterpret_cast<double*>(scratch + gbytes);
   int32_t* d_sg = reinterpret_cast<int32_t*>(scratch + gbytes + nbytes);
@@ -1106,7 +1129,7 @@ rt_status rt_trace_pm(const rt_cosmology* cosmo, double z_source, int32_t n_grid
   RT_HIP(hipStreamSynchronize(stream));   // the host staging above is pageable and local
   RT_HIP(launch_pm_trace(make_dev_cosmo(*cosmo), d_grids, d_sg, n_int, d_nodes, step_begin, se, rays,
                          9 * n_bundles, ray_flags, stream));
-  RT_HIP(hipFreeAsync(scratch, stream));
+  RT_HIP(sc.release());
   return RT_OK;
 }
 
@@ -1180,8 +1203,9 @@ rt_status rt_trace_pm_lambda_slabs(const rt_cosmology* cosmo, double z_source, i
   // scratch: grid table, then slab bounds, then slab grids
   const size_t gbytes = ((sizeof(DevPmGrid) * n_grids + 255) / 256) * 256;
   const size_t bbytes = ((sizeof(double) * (n_slabs + 1) + 255) / 256) * 256;
-  char* scratch = nullptr;
-  RT_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), gbytes + bbytes + sizeof(int32_t) * n_slabs, stream));
+  StreamScratch sc(stream);
+  RT_HIP(sc.alloc(gbytes + bbytes + sizeof(int32_t) * n_slabs));
+  char* scratch = static_cast<char*>(sc.p);
   DevPmGrid* d_grids = reinterpret_cast<DevPmGrid*>(scratch);
   double* d_bounds = reinterpret_cast<double*>(scratch + gbytes);
   int32_t* d_sg = reinterpret_cast<int32_t*>(scratch + gbytes + bbytes);
@@ -1192,7 +1216,7 @@ rt_status rt_trace_pm_lambda_slabs(const rt_cosmology* cosmo, double z_source, i
   RT_HIP(launch_pm_trace_lambda_slabs(make_dev_cosmo(*cosmo), d_grids, d_bounds, d_sg, n_slabs, grids[0].h, n_int,
                                       comoving_distance(*cosmo, z_source), f_rk, max_steps, rays, 9 * n_bundles,
                                       ray_flags, ray_steps, stream));
-  RT_HIP(hipFreeAsync(scratch, stream));
+  RT_HIP(sc.release());
   return RT_OK;
 }
 
