@@ -143,7 +143,8 @@ rt_status rt_build_bundles(const rt_cosmology* cosmo, const rt_field* fields, in
  * times the bundle's largest ray offset are summed per ray directly in FP64; the truncation of
  * the expansion stays below 6e-6 of each pair's ring difference.  Particle positions are held as
  * two FP32 parts.  A set whose masses are all equal (checked on the device at every call) skips
- * the per-pair mass product.
+ * the per-pair mass product.  Sets of at most 63 particles (point lenses) are summed per ray
+ * directly in FP64.
  * rays: device [8][9 n_bundles], updated in place.  ray_flags: device [9 n_bundles] or NULL;
  * bits are OR-ed in: 1 non-finite state, 2 kz <= 0 (ray turned back), 4 |phi|/a > 1e-2 (outside
  * the weak-field regime of Sec. 3.2).  A ray with flag 1 or 2 keeps its last good state.
@@ -302,7 +303,7 @@ rt_status rt_trace_pm_lambda_slabs(const rt_cosmology* cosmo, double z_source, i
 typedef struct rt_plan_info {
   int32_t waves_per_block;    /* wavefronts in one workgroup                                 */
   int32_t waves_per_group;    /* wavefronts that share 63 rays and split the particles      */
-  int32_t tile;               /* particles per LDS tile per wavefront                        */
+  int32_t tile;               /* particles per LDS tile (staged once per workgroup)          */
   int32_t rays_per_block;     /* 63 * waves_per_block / waves_per_group (7 bundles per group) */
   int32_t waves_per_simd;     /* occupancy the plan is compiled for (registers: 512 / it)    */
 } rt_plan_info;
