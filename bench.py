@@ -406,8 +406,14 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         b0 = bands[len(bands) // 2] if len(bands) > 1 else bands[0]
         nf = a.fp64_bundles or {"box20": 504, "box18": 1024, "nfw": 7168, "point": 1024}.get(a.workload, 0)
         if a.workload == "batched":
-            # the same 64 fields with 16 x 16 bundles each (the full grids would take an hour in FP64)
-            sub = workloads.batched(side_override=16)
+            # about 256 bundles of each field, strided over the field's own (64^2-256^2) grid: the
+            # full grids would take an hour in FP64
+            sub = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
+                                     [workloads.FieldSpec(f.name, f.sets,
+                                                          np.ascontiguousarray(
+                                                              f.theta[:, ::max(1, f.n_bundles // 256)][:, :256]),
+                                                          f.schedule, f.replica_box, dict(f.meta))
+                                      for f in w.fields])
         else:
             f = b0.fields[0]
             stride = max(1, f.n_bundles // nf)
@@ -433,8 +439,8 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         st = mu_stats(m32, m64)
         st["gate_1e-4"] = mu_gate(m32, m64, 1e-4)
         if a.workload == "batched":
-            st["bundles"] = ("%d bundles: the same 64 fields with 16 x 16 bundles each, whole schedules, both "
-                             "precisions on the GPU" % m64.size)
+            st["bundles"] = ("%d bundles: 256 of each of the 64 fields, strided over its own grid, whole "
+                             "schedules, both precisions on the GPU" % m64.size)
         else:
             st["bundles"] = ("%d bundles of the central band (every %d-th), whole schedule, both precisions on the "
                              "GPU" % (m64.size, max(1, b0.fields[0].n_bundles // max(nf, 1))))
@@ -442,15 +448,18 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         theta_sub = np.concatenate([f.theta for f in sub.fields], axis=1)
         result["exit_err_vs_fp64"] = exit_errors(r32, r64, theta_sub, w.bundle_radius, gs.chi_s)
         fp64 = {"subsample_mixed_ms": ms32, "subsample_fp64_ms": ms64}
-        # FP64 throughput at the timed launch shape: one full window of the first band
+        # FP64 throughput at the timed launch shape: one full window of the first band (the
+        # batched launch: its first 20 steps, which keeps one FP64 launch near 90 s)
         g.set_theta(thetas[0])
         g.build_bundles()
         s0, s1 = windows[0]
+        if a.workload == "batched":
+            s1 = s0 + min(20, s1 - s0)
         rt.rt_enable_timing(True)
         g.trace(rt.RT_FP64, s0, s1)
         info = rt.rt_last_trace_info()
         rt.rt_enable_timing(False)
-        rate64 = inter_win[0] / (info["kernel_ms"] * 1e-3)
+        rate64 = g.interactions(s0, s1) / (info["kernel_ms"] * 1e-3)
         rate32 = inter_launch / (k_ms * 1e-3)
         fp64.update({"interactions_per_s": rate64, "kernel_ms": info["kernel_ms"],
                      "shape": "%d bundles, RK4 steps [%d, %d)" % (per_step, s0, s1),
