@@ -451,17 +451,23 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
         # FP64 throughput at the timed launch shape: one full window of the first band (the
         # batched launch: its first 20 steps, which keeps one FP64 launch near 90 s)
         g.set_theta(thetas[0])
-        g.build_bundles()
         s0, s1 = windows[0]
         if a.workload == "batched":
             s1 = s0 + min(20, s1 - s0)
+        if not a.no_autotune:
+            # the FP64 plan tuned for this launch shape, as the FP32 one is
+            g.build_bundles()
+            p64 = rt.rt_autotune(g.cosmo, w.z_source, g.table, rt.RT_FP64, n_rk // 2,
+                                 1 if a.workload == "batched" else 2, g.n_bundles, g.rays)
+            say("fp64 autotune: plan %d %s" % (p64, rt.rt_plan_describe(rt.RT_FP64, p64)))
+        g.build_bundles()
         rt.rt_enable_timing(True)
         g.trace(rt.RT_FP64, s0, s1)
         info = rt.rt_last_trace_info()
         rt.rt_enable_timing(False)
         rate64 = g.interactions(s0, s1) / (info["kernel_ms"] * 1e-3)
         rate32 = inter_launch / (k_ms * 1e-3)
-        fp64.update({"interactions_per_s": rate64, "kernel_ms": info["kernel_ms"],
+        fp64.update({"interactions_per_s": rate64, "kernel_ms": info["kernel_ms"], "plan": info["plan_id"],
                      "shape": "%d bundles, RK4 steps [%d, %d)" % (per_step, s0, s1),
                      "tflops": FLOP_FP64 * rate64 / 1e12, "frac_of_fp64_peak": FLOP_FP64 * rate64 / 1e12 / PEAK_FP64,
                      "mixed_speedup": rate32 / rate64})

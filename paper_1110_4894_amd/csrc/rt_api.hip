@@ -346,12 +346,28 @@ Workload describe(const rt_field* fields, int32_t n_fields, int32_t sb, int32_t 
 
 // Default plan: split the particles over enough wavefronts to give every SIMD
 // at least four of them, while every share keeps several tiles.
+// Without a tuned plan: enough wavefronts for about four per SIMD (several
+// wavefronts share a ray group when there are few rays and many particles),
+// and for FP32 the larger tiles when the sets fill them.
 int heuristic_plan(bool fp64, const Workload& w, int n_cu) {
   const double waves = w.rays / 64.0;
-  const double target = 16.0 * n_cu;
+  const double target = 0.9 * 16.0 * n_cu;
   const int tile = plan_info(fp64, 0).tile;
   int wpr = 1;
   while (wpr < 8 && waves * wpr < target && w.mean_np >= 4.0 * tile * wpr * 2) wpr *= 2;
+  if (!fp64) {
+    // the plan of 8 wavefronts with this sharing and the largest tile the sets fill
+    int best = -1, best_tile = 0;
+    for (int id = 0; id < plan_count(false); ++id) {
+      const rt_plan_info p = plan_info(false, id);
+      if (p.waves_per_block == 8 && p.waves_per_group == wpr && p.waves_per_simd == 4 && p.tile > best_tile &&
+          w.mean_np >= 4.0 * p.tile) {
+        best = id;
+        best_tile = p.tile;
+      }
+    }
+    if (best >= 0) return best;
+  }
   switch (wpr) {
     case 1: return 0;
     case 2: return 1;
