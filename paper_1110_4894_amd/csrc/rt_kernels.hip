@@ -11,8 +11,8 @@
 //     rays a few parsecs away).  The nine lanes of a bundle split the
 //     particles; each (bundle, particle) pair is evaluated once, at the
 //     bundle's expansion point, as the pair's potential and field and their
-//     first and second derivatives (20 moments, 36 VALU instructions and one
-//     v_rsq_f32 per pair, i.e. 4 per ray-particle interaction).  Every ray
+//     first and second derivatives (20 moments, 39 VALU instructions per pair
+//     including one v_rsq_f32, i.e. 4.3 per ray-particle interaction).  Every ray
 //     assembles its own field in FP64 from the moments and its exact offset.
 //     Ring-minus-anchor field differences, which carry the lensing signal,
 //     so keep FP32 relative precision: rounding each particle-ray
