@@ -417,3 +417,50 @@ def test_lambda_integrator_through_a_stack_of_isolated_cubes_matches_oracle():
     assert defl.min() > 1e-6                         # the rays are deflected
     assert np.max(np.abs(mu.cpu().numpy() / omu - 1)) < 1e-7
     assert np.all(np.hypot(g[1] - orays[1], g[2] - orays[2]) <= 1e-7 * defl + 1e-12)
+
+
+def test_lambda_integrator_through_one_periodic_grid_matches_oracle():
+    """rt_trace_pm_lambda with a periodic grid (the field everywhere, App. B windows wrapping):
+    a clustered periodic box of side 3.2 Mpc whose field every ray crosses from the observer on
+    (bundles built with no mass at the observer, on both sides)."""
+    c, oc = rt.cosmology(), orc.cosmo()
+    z_s = 0.01
+    n, h = 16, 0.2
+    L = n * h
+    origin = np.array([-0.5 * L, -0.5 * L, 0.0])
+    rng = np.random.default_rng(77)
+    xyz = origin + np.mod(rng.normal(0.5 * L, 0.25 * L, (3000, 3)), L)
+    m = np.full(3000, 2e10)
+    grid, fields = _build_periodic(xyz, m, n, origin, h)
+    F = opm.periodic_field(opm.cic_deposit_periodic(xyz, m, origin, h, n), h)
+    ogrid = (F, opm.spline_y2_periodic(F, h), origin, h, True)
+    theta_h = np.array([[0.01, -0.02], [0.015, 0.005]])
+    radius = 0.05 * np.pi / 180 / 3600
+    nb = theta_h.shape[1]
+    dev = torch.device("cuda")
+    chi_s = rt.rt_comoving_distance(c, z_s)
+    empty = rt.FieldTable([{"sets": [], "z_nodes": np.array([0.0, chi_s]), "step_set": np.full(1, -1, np.int32),
+                            "bundle_offset": 0, "n_bundles": nb}])
+    rays = torch.empty((8, 9 * nb), dtype=torch.float64, device=dev)
+    rt.rt_build_bundles(c, empty, nb, torch.from_numpy(theta_h).to(dev), radius, rays)
+    flags = torch.zeros(9 * nb, dtype=torch.uint8, device=dev)
+    steps = torch.zeros(9 * nb, dtype=torch.int32, device=dev)
+    rt.rt_trace_pm_lambda(c, z_s, grid, fields, 2, 2.0, 10 ** 6, nb, rays, flags, steps)
+    mu = torch.empty(nb, dtype=torch.float64, device=dev)
+    rt.rt_magnification(c, z_s, nb, radius, rays, mu, None)
+    torch.cuda.synchronize()
+    print("    [pm] oracle lambda trace through one periodic grid", flush=True)
+    ochi = orc.comoving_distance(oc, z_s)
+    of = orc.Field([], np.array([0.0, ochi]), np.full(1, -1, np.int32), 0, nb)
+    orays = orc.build_bundles(oc, [of], theta_h, radius)
+    orays, oflags, osteps = opm.trace_pm_lambda_slabs(oc, ochi, orays, [ogrid], np.array([-np.inf, np.inf]),
+                                                      np.zeros(1, np.int64), h, 2, 2.0, 10 ** 6)
+    omu, _ = orc.magnification(ochi, orays, radius)
+    assert not oflags.any() and not flags.cpu().numpy().any()
+    assert np.array_equal(steps.cpu().numpy(), osteps)
+    g = rays.cpu().numpy()
+    th = np.repeat(theta_h, 9, axis=1)
+    defl = np.hypot(orays[1] - th[0] * ochi, orays[2] - th[1] * ochi)
+    assert defl.min() > 1e-7
+    assert np.max(np.abs(mu.cpu().numpy() / omu - 1)) < 1e-7
+    assert np.all(np.hypot(g[1] - orays[1], g[2] - orays[2]) <= 1e-7 * defl + 1e-12)
