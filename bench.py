@@ -60,12 +60,14 @@ PEAK_FP32 = 157.3      # TFLOP/s, MI355X FP32 vector (published)
 PEAK_FP64 = 78.6       # TFLOP/s, MI355X FP64 vector (published)
 # Algorithmic FLOP of the FP32 field sum per (bundle, particle) pair, evaluated once for the
 # bundle's nine rays: displacement from the expansion point with the two-part position (2 sub,
-# 2 add), s = |D|^2 + eps^2 (3 FMA = 6), rsqrt (1), 1/s (1), s^-3/2 (1), potential (1), field
-# (3 FMA = 6), W (1), s^-5/2 (1), its products with Dx, Dy (2), V (2 add, 1 FMA = 4),
-# T (5 FMA = 10), s^-7/2 (1), its products with Dx, Dy (2) and the three second products (3),
-# U (7 FMA = 14): 58; one more (the mass) for sets of unequal masses.
-FLOP_PER_PAIR_EQUAL = 58.0
-FLOP_PER_PAIR = 59.0
+# 2 add), s = |D|^2 + eps^2 (2 FMA = 4: z^2 + eps^2 is formed once per particle when the tile
+# is staged), rsqrt (1), 1/s (1), s^-3/2 (1), potential (1), field (3 FMA = 6), W (1),
+# s^-5/2 (1), its products with Dx, Dy (2), V (2 add, 1 FMA = 4), T (5 FMA = 10), the s^-7/2
+# products with Dx, Dy (2, from the s^-5/2 ones) and the three second products (3),
+# U (7 FMA = 14): 55.  Sets of unequal masses: the mass product (1) and z^2 + eps^2 per pair
+# (1 FMA = 2), 58.
+FLOP_PER_PAIR_EQUAL = 55.0
+FLOP_PER_PAIR = 58.0
 # The direct per-ray pair term (3 sub, 3 FMA, rsqrt, m/r, 1 add, 2 mul, 3 FMA): 20 FLOP per
 # ray-particle interaction.  Reported as the direct-sum equivalent rate.
 FLOP_DIRECT = 20.0
@@ -75,10 +77,10 @@ FLOP_FP64 = 20.0
 # one 25-step window of the 2^20 box), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain copy kernel, keyed by trace_kernel_code_sha of the kernel they were taken on.
 MEASURED_TRAFFIC = {
-    # trace_kernel<false, 8, 1, 2304, 4>: FETCH_SIZE 36839319.7 KiB x 1.9999, WRITE_SIZE 4132780.7 KiB x 1.0
-    "806a9ff206f12bf2": {"read": 75442978572.0, "write": 4231967392.0, "plan": 8},
-    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 40900581.1 KiB x 1.9999, WRITE_SIZE 3924915.7 KiB x 1.0
-    "2ea94e3e9d846031": {"read": 83760006742.0, "write": 4019113632.0, "plan": 4},
+    # trace_kernel<false, 8, 1, 2304, 4>: FETCH_SIZE 36617326.3 KiB x 1.9999, WRITE_SIZE 4132780.3 KiB x 1.0
+    "b87740cf0a5c5e6b": {"read": 74988243727.0, "write": 4231966976.0, "plan": 8},
+    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 37424089.6 KiB x 1.9999, WRITE_SIZE 3924916.6 KiB x 1.0
+    "efb09431c907a801": {"read": 76640405840.0, "write": 4019114560.0, "plan": 4},
 }
 
 

@@ -11,8 +11,9 @@
 //     rays a few parsecs away).  The nine lanes of a bundle split the
 //     particles; each (bundle, particle) pair is evaluated once, at the
 //     bundle's expansion point, as the pair's potential and field and their
-//     first and second derivatives (20 moments, 39 VALU instructions per pair
-//     including one v_rsq_f32, i.e. 4.3 per ray-particle interaction).  Every ray
+//     first and second derivatives (20 moments, 37 VALU instructions per pair
+//     of a set of equal masses including one v_rsq_f32, i.e. 4.1 per
+//     ray-particle interaction).  Every ray
 //     assembles its own field in FP64 from the moments and its exact offset.
 //     Ring-minus-anchor field differences, which carry the lensing signal,
 //     so keep FP32 relative precision: rounding each particle-ray
@@ -183,16 +184,22 @@ enum : int {
   M_UXXX, M_UXXY, M_UXYY, M_UYYY, M_UZXX, M_UZXY, M_UZYY
 };
 
-// One (bundle, particle) pair.  p = (x, y, z relative to e, m / mref) with x, y
-// still in the set's frame, lo = the residuals of x and y; (ex, ey) = e.  DETECT: return whether the pair is
-// near (s < thr); EXCLUDE: also leave a near pair out of the moments.
+// One (bundle, particle) pair.  p = (x, y, z relative to e, w) with x, y still
+// in the set's frame and w = m / mref, or for a set of equal masses (whose pairs
+// need no mass) w = z^2 + eps^2, staged once per particle; lo = the residuals of
+// x and y; (ex, ey) = e.  DETECT: return whether the pair is near (s < thr);
+// EXCLUDE: also leave a near pair out of the moments.
+template <bool EQUAL>
+__device__ __forceinline__ float pair_s(const float4 p, float Dx, float Dy, float e2) {
+  const float sz = EQUAL ? p.w : fmaf(p.z, p.z, e2);
+  return fmaf(Dx, Dx, fmaf(Dy, Dy, sz));
+}
+
 template <bool EQUAL, bool DETECT, bool EXCLUDE>
 __device__ __forceinline__ bool moment_terms(const float4 p, const float2 lo, float ex, float ey, float e2,
                                              float thr, float (&a)[kMom]) {
   const float Dx = (p.x - ex) + lo.x, Dy = (p.y - ey) + lo.y, Dz = p.z;
-  float s = fmaf(Dx, Dx, e2);
-  s = fmaf(Dy, Dy, s);
-  s = fmaf(Dz, Dz, s);
+  const float s = pair_s<EQUAL>(p, Dx, Dy, e2);
   float ia = __builtin_amdgcn_rsqf(s);
   const bool near = (DETECT || EXCLUDE) && s < thr;
   if constexpr (EXCLUDE) ia = near ? 0.f : ia;
@@ -214,8 +221,8 @@ __device__ __forceinline__ bool moment_terms(const float4 p, const float2 lo, fl
   a[M_TYY] = fmaf(Dy, qy, a[M_TYY]);
   a[M_TZX] = fmaf(Dz, qx, a[M_TZX]);
   a[M_TZY] = fmaf(Dz, qy, a[M_TZY]);
-  const float r = q * ia2;
-  const float rx = r * Dx, ry = r * Dy;
+  // m s^-7/2 (Dx, Dy), from the s^-5/2 products
+  const float rx = qx * ia2, ry = qy * ia2;
   const float rxx = rx * Dx, rxy = rx * Dy, ryy = ry * Dy;
   a[M_UXXX] = fmaf(Dx, rxx, a[M_UXXX]);
   a[M_UXXY] = fmaf(Dx, rxy, a[M_UXXY]);
@@ -237,9 +244,7 @@ template <bool EQUAL>
 __device__ __forceinline__ void near_direct(const float4 p, const float2 lo, float ex, float ey, float e2,
                                             float thr, float dx, float dy, float dz, double (&d)[4]) {
   const float Dx = (p.x - ex) + lo.x, Dy = (p.y - ey) + lo.y, Dz = p.z;
-  float s = fmaf(Dx, Dx, e2);
-  s = fmaf(Dy, Dy, s);
-  s = fmaf(Dz, Dz, s);
+  const float s = pair_s<EQUAL>(p, Dx, Dy, e2);
   if (!(s < thr)) return;
   // FP64 from here: the displacement from the particle's two-part position is
   // exact, and the term's rounding stays far below its ring-minus-anchor difference
@@ -305,18 +310,20 @@ __device__ __forceinline__ void moment_tiles(const DevSet& s, float4* tile, int 
     const int64_t ch = q + it * WPR;
     const int64_t base = ch * TP;
     // Stage: positions in the set's frame (two parts for x and y), z relative
-    // to the stage's z.  Padding past the end lies so far away that s
-    // overflows to +inf, whose reciprocal square root is +0.
+    // to the stage's z, and for equal masses z^2 + eps^2 in place of the mass.
+    // Padding past the end lies so far away that s overflows to +inf, whose
+    // reciprocal square root is +0.
     if (ch < n_tiles) {
 #pragma unroll
       for (int k = 0; k < (TP + NG * 64 - 1) / (NG * 64); ++k) {
         const int j = g * 64 + lane + NG * 64 * k;
         if (j < TP) {
-          float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+          float4 v = make_float4(1e30f, 1e30f, 1e30f, EQUAL ? __builtin_inff() : 0.f);
           float2 vl = make_float2(0.f, 0.f);
           if (base + j < n) {
             const float4 p = src[base + j], r = src_lo[base + j];
-            v = make_float4(p.x, p.y, (p.z - zr_hi) + (r.z - zr_lo), p.w);
+            const float zs = (p.z - zr_hi) + (r.z - zr_lo);
+            v = make_float4(p.x, p.y, zs, EQUAL ? fmaf(zs, zs, e2) : p.w);
             vl = make_float2(r.x, r.y);
           }
           tile[j] = v;
