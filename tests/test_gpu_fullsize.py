@@ -229,7 +229,7 @@ def test_set_beyond_32bit_offsets():
 def test_benchmark_launch_against_the_oracle():
     """The launch bench.py times by default: the first 28672-bundle band of the 2^20 box's
     512 x 512 grid through the first 25-step window, with the plan the autotuner picks for it
-    (one wavefront per 7 bundles, 1152-particle tiles, 512 workgroups).  16 seeded bundles of the
+    (one wavefront per 7 bundles, 2304-particle tiles, 512 workgroups).  16 seeded bundles of the
     band against the oracle traced through the same window: positions and directions, each
     relative to its change from the straight ray (a straight ray keeps x = (kx / kz) z).  (The
     bundles' own lensing signal, the ring-minus-anchor offsets, is still below 1e-12 Mpc this
@@ -242,7 +242,7 @@ def test_benchmark_launch_against_the_oracle():
     wb = _with_theta(w, [f.theta[:, :band]])
     plans = [i for i in range(rt.rt_plan_count(FP32K))
              if rt.rt_plan_describe(FP32K, i)["waves_per_group"] == 1
-             and rt.rt_plan_describe(FP32K, i)["tile"] == 1152 and rt.rt_plan_describe(FP32K, i)["waves_per_block"] == 8]
+             and rt.rt_plan_describe(FP32K, i)["tile"] == 2304 and rt.rt_plan_describe(FP32K, i)["waves_per_block"] == 8]
     assert plans
     rt.rt_force_plan(FP32K, plans[0])
     try:
