@@ -79,8 +79,8 @@ FLOP_FP64 = 20.0
 MEASURED_TRAFFIC = {
     # trace_kernel<false, 8, 1, 2304, 4>: FETCH_SIZE 36617326.3 KiB x 1.9999, WRITE_SIZE 4132780.3 KiB x 1.0
     "b87740cf0a5c5e6b": {"read": 74988243727.0, "write": 4231966976.0, "plan": 8},
-    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 37424089.6 KiB x 1.9999, WRITE_SIZE 3924916.6 KiB x 1.0
-    "efb09431c907a801": {"read": 76640405840.0, "write": 4019114560.0, "plan": 4},
+    # trace_kernel<false, 8, 1, 1152, 4>: FETCH_SIZE 55417972.5 KiB x 1.9999, WRITE_SIZE 4330366.2 KiB x 1.0
+    "6bc73458edfaf096": {"read": 113489892550.0, "write": 4434295008.0, "plan": 4},
 }
 
 

@@ -144,7 +144,7 @@ __device__ __forceinline__ int lane_segment(int lane) { return lane < kLanes ? l
 // (boxes: 71 kpc against a few parsecs) skip the nearness test altogether.
 // ===========================================================================
 constexpr int kMom = 20;
-constexpr int kKahanRounds = 64;         // rounds of plain FP32 sums between compensated adds
+constexpr int kKahanRounds = 256;        // rounds of plain FP32 sums between compensated adds (unguarded sums)
 constexpr float kNearRatio2 = 1048576.f;   // (1024)^2
 constexpr float kNearFloor2 = 1e-8f;     // (1e-4 Mpc)^2
 // LDS bytes per wavefront of the FP32 path: its tile, and at least what its
