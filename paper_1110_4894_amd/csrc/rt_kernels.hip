@@ -152,7 +152,8 @@ constexpr float kNearFloor2 = 1e-8f;     // (1e-4 Mpc)^2
 // the group's [20][7] double totals).
 // LDS of the FP32 path, per workgroup: WPR tiles (one per wavefront index q of
 // the ray groups; the NG groups of a workgroup share them), each TP float4
-// (x, y in the set's frame, z relative to the stage, m) followed by TP float2
+// (x, y in the set's frame, z relative to the stage, m, or z^2 + eps^2 for a
+// set of equal masses) followed by TP float2
 // (the rounding residuals of x and y).  After the last tile the same bytes hold
 // the moment reduction: per wavefront [20][64] floats, [4][64] doubles and, per
 // group, [20][7] double totals.
