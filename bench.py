@@ -404,8 +404,8 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
 
     # ---------------------------------------------------------------- mixed vs FP64 on the same bundles
     if not a.no_fp64 and prec != rt.RT_FP64:
-        # the band through the centre of the bundle grid (the halo core for the NFW workload)
-        b0 = bands[len(bands) // 2] if len(bands) > 1 else bands[0]
+        # a band of the step's size centred on the middle of the bundle grid (for the NFW workload,
+        # the rows through the halo core), whatever band the timed steps ended on
         nf = a.fp64_bundles or {"box20": 504, "box18": 1024, "nfw": 7168, "point": 1024}.get(a.workload, 0)
         if a.workload == "batched":
             # about 256 bundles of each field, strided over the field's own (64^2-256^2) grid: the
@@ -417,11 +417,13 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
                                                           f.schedule, f.replica_box, dict(f.meta))
                                       for f in w.fields])
         else:
-            f = b0.fields[0]
-            stride = max(1, f.n_bundles // nf)
+            f = w.fields[0]
+            c0 = max(0, f.n_bundles // 2 - per_step // 2)
+            th_band = f.theta[:, c0:c0 + per_step]
+            stride = max(1, th_band.shape[1] // nf)
             sub = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
                                      [workloads.FieldSpec(f.name, f.sets,
-                                                          np.ascontiguousarray(f.theta[:, ::stride][:, :nf]),
+                                                          np.ascontiguousarray(th_band[:, ::stride][:, :nf]),
                                                           f.schedule, f.replica_box, {})])
         gs = GpuRun(sub, uploads=uploads)
         outs = {}
@@ -444,8 +446,9 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
             st["bundles"] = ("%d bundles: 256 of each of the 64 fields, strided over its own grid, whole "
                              "schedules, both precisions on the GPU" % m64.size)
         else:
-            st["bundles"] = ("%d bundles of the central band (every %d-th), whole schedule, both precisions on the "
-                             "GPU" % (m64.size, max(1, b0.fields[0].n_bundles // max(nf, 1))))
+            st["bundles"] = ("%d bundles of the central band (bundles %d-%d of the grid, every %d-th), whole "
+                             "schedule, both precisions on the GPU" % (m64.size, c0, c0 + th_band.shape[1] - 1,
+                                                                      stride))
         result["mu_err_vs_fp64"] = st
         theta_sub = np.concatenate([f.theta for f in sub.fields], axis=1)
         result["exit_err_vs_fp64"] = exit_errors(r32, r64, theta_sub, w.bundle_radius, gs.chi_s)
