@@ -202,6 +202,18 @@ def batches(w, a):
     return out, band
 
 
+def central_band(theta, per_step, n_compare):
+    """The bundles compared between the mixed and FP64 runs: a band of per_step bundles
+    centred on the middle of the row-major bundle grid theta [2][n] (for the NFW halo, the
+    rows through its core), every stride-th of it up to n_compare.  Returns (theta of those
+    bundles, first and last grid index of the band, stride)."""
+    n = theta.shape[1]
+    c0 = max(0, n // 2 - per_step // 2)
+    band = theta[:, c0:c0 + per_step]
+    stride = max(1, band.shape[1] // max(n_compare, 1))
+    return np.ascontiguousarray(band[:, ::stride][:, :n_compare]), c0, c0 + band.shape[1] - 1, stride
+
+
 def equal_mass_fraction(g):
     """Fraction of the (bundle, particle) pairs of a GpuRun whose set has equal masses."""
     tot = eq = 0.0
@@ -418,13 +430,9 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
                                       for f in w.fields])
         else:
             f = w.fields[0]
-            c0 = max(0, f.n_bundles // 2 - per_step // 2)
-            th_band = f.theta[:, c0:c0 + per_step]
-            stride = max(1, th_band.shape[1] // nf)
+            th_cmp, c0, c1, stride = central_band(f.theta, per_step, nf)
             sub = workloads.Workload(w.name, w.cosmology, w.z_source, w.bundle_radius,
-                                     [workloads.FieldSpec(f.name, f.sets,
-                                                          np.ascontiguousarray(th_band[:, ::stride][:, :nf]),
-                                                          f.schedule, f.replica_box, {})])
+                                     [workloads.FieldSpec(f.name, f.sets, th_cmp, f.schedule, f.replica_box, {})])
         gs = GpuRun(sub, uploads=uploads)
         outs = {}
         for p_ in (rt.RT_FP32_KAHAN, rt.RT_FP64):
@@ -447,8 +455,7 @@ def bench_direct(a, torch, rt, workloads, GpuRun, dev):
                              "schedules, both precisions on the GPU" % m64.size)
         else:
             st["bundles"] = ("%d bundles of the central band (bundles %d-%d of the grid, every %d-th), whole "
-                             "schedule, both precisions on the GPU" % (m64.size, c0, c0 + th_band.shape[1] - 1,
-                                                                      stride))
+                             "schedule, both precisions on the GPU" % (m64.size, c0, c1, stride))
         result["mu_err_vs_fp64"] = st
         theta_sub = np.concatenate([f.theta for f in sub.fields], axis=1)
         result["exit_err_vs_fp64"] = exit_errors(r32, r64, theta_sub, w.bundle_radius, gs.chi_s)
