@@ -19,9 +19,10 @@
 //     so keep FP32 relative precision: rounding each particle-ray
 //     displacement to FP32 instead would quantise the ring offset to the ulp
 //     of a Mpc-scale distance, identically for every particle of a binade;
-//   * plain FP32 partial sums over each tile are added with Kahan
-//     compensation; FP64 is kept for the ray state, the integration and the
-//     assembly of each ray's field;
+//   * plain FP32 partial sums over 256 rounds of a bundle's nine lanes (one
+//     or more tiles; one tile when the nearness test runs) are added with
+//     Kahan compensation; FP64 is kept for the ray state, the integration and
+//     the assembly of each ray's field;
 //   * the pairwise sum is not a dense contraction: no matrix cores;
 //   * work items (field, block of rays) are pulled from an atomic queue so that
 //     fields of very different particle counts share one launch.
